@@ -1,0 +1,346 @@
+"""Pins of the CPU oracle (oracle/dm.py) against results fixed by the paper and by
+mathematics, none of which reuses the oracle's own formulas:
+
+P1  brute-force enumeration on tiny networks (exact at full chi)
+P3  transfer-matrix values on narrow lattices (the method is exact once chi
+    reaches the full bond dimension)
+P4  the canonicalisation twin (paper: the density-matrix and canonicalisation
+    algorithms give the same truncated network) at chi below full
+P5  Onsager's closed-form free energy via a second difference that cancels the
+    surface and corner terms of open lattices
+P6  symmetric, PSD density matrices
+P7  gauge freedom: rotating every kept basis changes nothing
+P8  the log path: scaling an input tensor by c shifts lnZ by ln c
+P9  #CSP closed form for disjoint clauses
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2406_09769_amd import inputs
+from oracle import canon, dm, exact
+
+
+# ------------------------------------------------------------------ keep rule
+
+def test_keep_basic_and_cutoffs():
+    w = np.array([4.0, 2.0, 1.0, 0.5, 1e-17, 0.0])
+    q, _ = np.linalg.qr(np.random.default_rng(0).standard_normal((6, 6)))
+    L = q @ np.diag(w) @ q.T
+    U, ws, k, fb = dm.keep(L, 3)
+    assert k == 3 and not fb
+    assert np.allclose(np.abs(U.T @ q[:, :3]), np.eye(3), atol=1e-12)
+    _, _, k, _ = dm.keep(L, 10)          # numerical zeros dropped
+    assert k == 4
+
+
+def test_keep_does_not_split_a_degenerate_cluster():
+    w = np.array([1.0, 0.3, 0.3, 0.1])
+    L = np.diag(w)
+    _, _, k, _ = dm.keep(L, 2)
+    assert k == 1                         # cutting between the two 0.3 would split the cluster
+    _, _, k, _ = dm.keep(L, 3)
+    assert k == 3
+
+
+def test_keep_is_blind_to_zero_padding():
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal((5, 5))
+    L = a @ a.T
+    Lp = np.zeros((9, 9))
+    Lp[:5, :5] = L
+    for chi in (2, 4, 5, 8):
+        assert dm.keep(L, chi)[2] == dm.keep(Lp, chi)[2]
+
+
+def test_keep_all_zero_falls_back():
+    _, _, k, fb = dm.keep(np.zeros((4, 4)), 3)
+    assert fb and k == 3
+
+
+# ------------------------------------------------------------------ P1 brute force
+
+@pytest.mark.parametrize("env", [1, 2])
+def test_p1_2d_full_chi_matches_brute_force(env):
+    net = inputs.ising_2d(4, 4, 0.44)
+    bf = exact.brute_force_ising(16, net.meta["bonds"], net.meta["couplings"], 0.44)
+    v, s = dm.contract_approx(net, 16, env, tau_rel=0, tau_deg=0)
+    assert s == 1 and abs(v - bf) <= 1e-12 * abs(bf)
+
+
+def test_p1_3d_full_chi_matches_brute_force():
+    net = inputs.ising_3d(2, 3, 3, 0.2217)
+    bf = exact.brute_force_ising(18, net.meta["bonds"], net.meta["couplings"], 0.2217)
+    v, s = dm.contract_approx(net, 512, 1, tau_rel=0, tau_deg=0)
+    assert s == 1 and abs(v - bf) <= 1e-12 * abs(bf)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_p1_signed_rrg_full_chi_matches_brute_force(seed):
+    net = inputs.ising_rrg(16, 1.0, seed=seed)
+    bf = exact.brute_force_ising(16, net.meta["bonds"], net.meta["couplings"], 1.0)
+    v, s = dm.contract_approx(net, 256, 1, tau_rel=0, tau_deg=0)
+    assert s == 1 and abs(v - bf) <= 1e-12 * abs(bf)
+    v3, _ = dm.contract_approx(net, 256, 3, tau_rel=0, tau_deg=0)
+    assert abs(v3 - bf) <= 1e-12 * abs(bf)
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_p1_csp_full_chi_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    clauses = inputs.random_3sat(10, 16, rng)
+    net = inputs.csp_network(10, clauses)
+    count = exact.brute_force_count(10, clauses)
+    assert count > 0
+    v, s = dm.contract_approx(net, 256, 1, tau_rel=0, tau_deg=0)
+    assert s == 1 and abs(v - math.log(count)) <= 1e-12 * math.log(count)
+
+
+def test_p1_unsatisfiable_csp_is_zero_to_rounding():
+    # (x0, x1, x2) under all 8 sign patterns: no solution. Projections mix signs, so
+    # Z = 0 comes back at the rounding level of the 2^4 assignments, not exactly.
+    clauses = [[(0, a), (1, b), (2, c)] for a in (False, True) for b in (False, True) for c in (False, True)]
+    net = inputs.csp_network(4, clauses)
+    v, s = dm.contract_approx(net, 16, 1)
+    assert v < math.log(16.0) + math.log(1e-12)
+
+
+def test_p1_zero_tensor_gives_exact_zero():
+    net = inputs.ising_2d(5, 5, 0.44)
+    net.tensors[12] = np.zeros_like(net.tensors[12])
+    assert dm.contract_approx(net, 4, 1) == (-math.inf, 0)
+
+
+# ------------------------------------------------------------------ P3 exact at full chi
+
+@pytest.mark.parametrize("env", [1, 2])
+def test_p3_6x6_exact_at_full_chi(env):
+    net = inputs.ising_2d(6, 6, 0.44)
+    ex = exact.tm_2d(6, 6, 0.44)
+    v, _ = dm.contract_approx(net, 16, env, tau_rel=0, tau_deg=0)
+    assert abs(v - ex) / 36 <= 1e-13
+    v, _ = dm.contract_approx(net, 16, env)          # default cutoffs
+    assert abs(v - ex) / 36 <= 1e-13
+
+
+def test_p3_narrow_strip_exact_at_chi64():
+    # 64 rows of width 12: 12 leaves, full bond 2^6 = 64
+    net = inputs.ising_2d(64, 12, 0.44)
+    ex = exact.tm_2d(64, 12, 0.44)
+    v, _ = dm.contract_approx(net, 64, 1, tau_rel=0, tau_deg=0)
+    assert abs(v - ex) / net.n_sites <= 1e-13
+    v, _ = dm.contract_approx(net, 64, 1)
+    assert abs(v - ex) / net.n_sites <= 1e-11
+
+
+def test_p3_3d_slab_exact_at_full_chi():
+    net = inputs.ising_3d(4, 3, 3, 0.2217)
+    ex = exact.tm_3d(4, 3, 3, 0.2217)
+    v, _ = dm.contract_approx(net, 32, 1, tau_rel=0, tau_deg=0)
+    assert abs(v - ex) / net.n_sites <= 1e-13
+
+
+def test_truncation_error_decreases_with_chi():
+    net = inputs.ising_2d(8, 8, 0.44)
+    ex = exact.tm_2d(8, 8, 0.44)
+    errs = [abs(dm.contract_approx(net, chi, 1)[0] - ex) for chi in (1, 2, 4, 8)]
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[-1] < 1e-6
+
+
+def test_larger_environment_is_not_worse():
+    # the paper's environment study: a larger partition lowers the error at equal chi
+    net = inputs.ising_2d(10, 10, 0.44)
+    ex = exact.tm_2d(10, 10, 0.44)
+    e1 = abs(dm.contract_approx(net, 4, 1)[0] - ex)
+    e2 = abs(dm.contract_approx(net, 4, 2)[0] - ex)
+    assert e2 < e1
+
+
+# ------------------------------------------------------------------ P4 canonicalisation twin
+
+@pytest.mark.parametrize("ly,lx,beta,chi,env", [
+    (6, 6, 0.44, 4, 1), (6, 6, 0.44, 2, 2), (8, 8, 0.44, 4, 1), (8, 8, 0.6, 3, 2),
+    (8, 10, 0.3, 3, 1)])
+def test_p4_2d_matches_canonicalisation(ly, lx, beta, chi, env):
+    net = inputs.ising_2d(ly, lx, beta)
+    v, _ = dm.contract_approx(net, chi, env)
+    c, _ = canon.contract_canon(net, chi, env)
+    assert abs(v - c) <= 1e-12 * abs(v)
+    assert abs(v - exact.tm_2d(ly, lx, beta)) > 1e-9       # really approximate
+
+
+def test_p4_3d_matches_canonicalisation():
+    net = inputs.ising_3d(3, 3, 3, 0.25)
+    v, _ = dm.contract_approx(net, 6, 1)
+    c, _ = canon.contract_canon(net, 6, 1)
+    assert abs(v - c) <= 1e-12 * abs(v)
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_p4_rrg_matches_canonicalisation(seed):
+    net = inputs.ising_rrg(24, 1.0, seed=seed)
+    for chi, env in ((4, 1), (6, 2)):
+        v, sv = dm.contract_approx(net, chi, env)
+        c, sc = canon.contract_canon(net, chi, env)
+        assert sv == sc and abs(v - c) <= 1e-11 * abs(v)
+
+
+def test_p4_csp_matches_canonicalisation():
+    rng = np.random.default_rng(41)
+    net = inputs.csp_network(20, inputs.random_3sat(20, 50, rng))
+    v, sv = dm.contract_approx(net, 4, 1)
+    c, sc = canon.contract_canon(net, 4, 1)
+    assert sv == sc and abs(v - c) <= 1e-11 * max(1.0, abs(v))
+
+
+# ------------------------------------------------------------------ P5 Onsager
+
+def _second_difference(fn, L):
+    return fn(L + 1, L + 1) - fn(L + 1, L) - fn(L, L + 1) + fn(L, L)
+
+
+def test_p5_transfer_matrix_second_difference_matches_onsager():
+    f = exact.onsager_f(0.30)
+    d2 = _second_difference(lambda a, b: exact.tm_2d(a, b, 0.30), 13)
+    assert abs(d2 - f) < 1e-10
+
+
+def test_p5_oracle_second_difference_matches_onsager():
+    f = exact.onsager_f(0.30)
+    d2 = _second_difference(lambda a, b: dm.contract_approx(inputs.ising_2d(a, b, 0.30), 32, 1)[0], 13)
+    assert abs(d2 - f) < 1e-9
+
+
+def test_p5_onsager_forms_agree_and_loose_band():
+    for b in (0.30, 0.44, 0.60):
+        assert abs(exact.onsager_f(b) - exact.onsager_f_double(b)) < 1e-12
+    # open 24x24 lattice: lnZ/N within the surface band of f
+    for b in (0.30, 0.60):
+        v, _ = dm.contract_approx(inputs.ising_2d(24, 24, b), 16, 1)
+        assert abs(v / 576 - exact.onsager_f(b)) < 0.12
+
+
+# ------------------------------------------------------------------ P6 / P7 / P8 / P9
+
+def test_p6_density_matrices_symmetric_psd():
+    st = dm.Stats()
+    dm.contract_approx(inputs.ising_2d(8, 8, 0.44), 8, 2, stats=st)
+    assert st.n_eig > 0
+    assert st.max_asym < 1e-13
+    assert st.min_ratio > -1e-13
+
+
+def test_p7_gauge_rotation_leaves_result_unchanged():
+    net = inputs.ising_2d(7, 7, 0.44)
+    v, _ = dm.contract_approx(net, 5, 1)
+    g, _ = dm.contract_approx(net, 5, 1, gauge_rng=np.random.default_rng(5))
+    assert abs(v - g) <= 1e-12 * abs(v)
+
+
+def test_p8_scaling_an_input_shifts_lnz():
+    net = inputs.ising_2d(6, 6, 0.44)
+    v, _ = dm.contract_approx(net, 4, 1)
+    net.tensors[7] = net.tensors[7] * 3.7
+    v2, _ = dm.contract_approx(net, 4, 1)
+    assert abs((v2 - v) - math.log(3.7)) <= 1e-13 * abs(v)
+    net.tensors[20] = net.tensors[20] * 2.0 ** 40
+    v3, _ = dm.contract_approx(net, 4, 1)
+    assert abs((v3 - v2) - 40 * math.log(2.0)) <= 1e-13 * abs(v)
+
+
+def test_p8_negative_input_flips_sign():
+    net = inputs.ising_2d(5, 5, 0.44)
+    v, s = dm.contract_approx(net, 4, 1)
+    net.tensors[3] = -net.tensors[3]
+    v2, s2 = dm.contract_approx(net, 4, 1)
+    assert s == 1 and s2 == -1 and abs(v - v2) < 1e-12 * abs(v)
+
+
+@pytest.mark.parametrize("m,n", [(3, 9), (4, 15), (5, 16)])
+def test_p9_disjoint_clauses_closed_form(m, n):
+    rng = np.random.default_rng(m * 100 + n)
+    perm = rng.permutation(n)
+    clauses = [[(int(perm[3 * i + a]), bool(rng.integers(0, 2))) for a in range(3)] for i in range(m)]
+    net = inputs.csp_network(n, clauses)
+    v, s = dm.contract_approx(net, 4, 1)
+    want = m * math.log(7.0) + (n - 3 * m) * math.log(2.0)
+    assert s == 1 and abs(v - want) <= 1e-13 * want
+
+
+# ------------------------------------------------------------------ planner structure
+
+def test_plan_2d_rows_are_column_ordered():
+    net = inputs.ising_2d(5, 6, 0.44)
+    st = dm.Stats()
+    dm.contract_approx(net, 4, 1, stats=st)
+    lx = 6
+    for j, (leaf_edges, placement) in enumerate(st.plans[:-1]):
+        cols = []
+        for e in leaf_edges:
+            t0, _, t1, _ = net.edges[e]
+            cols.append(min(t0, t1) % lx)
+        assert cols == list(range(lx))
+        sites = [(ref, p) for kind, ref, p in placement if kind == 'site']
+        assert all(p == ref % lx + 1 for ref, p in sites)
+    assert st.plans[-1][0] == []
+
+
+def test_plan_2d_two_row_partitions_are_column_ordered():
+    net = inputs.ising_2d(6, 5, 0.44)
+    st = dm.Stats()
+    dm.contract_approx(net, 4, 2, stats=st)
+    for leaf_edges, placement in st.plans[:-1]:
+        cols = [min(net.edges[e][0], net.edges[e][2]) % 5 for e in leaf_edges]
+        assert cols == list(range(5))
+        for kind, ref, p in placement:
+            if kind == 'site':
+                assert p == ref % 5 + 1
+
+
+def test_plan_3d_planes_are_row_major():
+    net = inputs.ising_3d(3, 3, 4, 0.25)
+    st = dm.Stats()
+    dm.contract_approx(net, 4, 1, stats=st)
+    for leaf_edges, _ in st.plans[:-1]:
+        sites = [min(net.edges[e][0], net.edges[e][2]) % 12 for e in leaf_edges]
+        assert sites == list(range(12))
+
+
+# ------------------------------------------------------------------ planted mistakes
+
+def test_pins_catch_a_wrong_eigenvector_choice(monkeypatch):
+    net = inputs.ising_2d(6, 6, 0.44)
+    good = canon.contract_canon(net, 3, 1)[0]
+    real_keep = dm.keep
+
+    def bad_keep(L, chi, *a):
+        U, w, k, fb = real_keep(L, chi, *a)
+        wv, v = np.linalg.eigh(L)
+        return v[:, :k], w, k, fb          # smallest eigenvectors instead of the leading ones
+    monkeypatch.setattr(dm, "keep", bad_keep)
+    assert abs(dm.contract_approx(net, 3, 1)[0] - good) > 1e-6
+
+
+def test_pins_catch_a_dropped_scale(monkeypatch):
+    net = inputs.ising_2d(4, 4, 0.44)
+    bf = exact.brute_force_ising(16, net.meta["bonds"], net.meta["couplings"], 0.44)
+
+    def bad_rescale(t):
+        m = float(np.max(np.abs(t.data)))
+        _, e = math.frexp(m)
+        return t, e                         # exponent counted but data left unscaled
+    monkeypatch.setattr(dm, "rescale", bad_rescale)
+    assert abs(dm.contract_approx(net, 16, 1)[0] - bf) > 1e-3
+
+
+def test_pins_catch_an_unprimed_bra(monkeypatch):
+    net = inputs.ising_2d(4, 4, 0.44)
+    bf = exact.brute_force_ising(16, net.meta["bonds"], net.meta["couplings"], 0.44)
+    monkeypatch.setattr(dm, "_bra", lambda lab, leaf: lab if lab == leaf or lab[0] == 'b' else ('bra', lab))
+    try:
+        caught = abs(dm.contract_approx(net, 16, 1)[0] - bf) > 1e-9
+    except AssertionError:
+        caught = True                       # the oracle's own label checks fire
+    assert caught
