@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Throughput of the density-matrix approximate contraction on one MI355X.
+
+Workload (one step): the 64x64 open 2D Ising lattice (J=1, h=0) at the 8 inverse
+temperatures linspace(0.30, 0.60, 8), each at max_rank chi in {32, 64} and
+env_size in {1, 2}: 32 networks, contracted in ONE persistent launch (one
+workgroup per network). Inputs are uploaded once before timing (tn_create).
+
+Prints one JSON line: networks/s over the timed steps, the roofline of the
+interpreter kernel (algorithmic GEMM flops per launch over its HIP-event
+duration), the per-site error of every result against the stored oracle values,
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "networks/s + MFMA util at |dlnZ|/N<=1e-8: mixed+batched+learned vs plain FP64"
+PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 (matrix and vector)
+HBM_PEAK_GBS = 8000.0
+GROUPS = [(32, 1), (32, 2), (64, 1), (64, 2)]
+
+
+def workload():
+    from paper_2406_09769_amd import inputs
+    nets, chis, envs = [], [], []
+    for chi, env in GROUPS:
+        for beta in inputs.w2_betas():
+            nets.append(inputs.ising_2d(64, 64, beta))
+            chis.append(chi)
+            envs.append(env)
+    return nets, chis, envs
+
+
+def golden_errors(results, chis, envs):
+    path = os.path.join(ROOT, "tests", "golden", "w2_oracle.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2406_09769_amd import inputs
+    gold = json.load(open(path))["rows"]
+    betas = inputs.w2_betas() * len(GROUPS)
+    errs = []
+    for r, chi, env, b in zip(results, chis, envs, betas):
+        g = next(x for x in gold if x["chi"] == chi and x["env"] == env and abs(x["beta"] - b) < 1e-12)
+        errs.append(abs(r.log_abs - g["log_abs"]) / 4096 if r.sign == g["sign"] else float("inf"))
+    return errs
+
+
+def cpu_baseline(sample: int):
+    """The oracle, untuned, on `sample` networks of the same workload (host cores)."""
+    import numpy as np  # noqa: F401
+    from paper_2406_09769_amd import inputs
+    from oracle import dm
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:
+        threads = os.cpu_count()
+    picks = []
+    betas = inputs.w2_betas()
+    for i in range(sample):
+        chi, env = GROUPS[i % len(GROUPS)]
+        picks.append((chi, env, betas[(3 * i + 3) % len(betas)]))
+    t0 = time.perf_counter()
+    for chi, env, b in picks:
+        dm.contract_approx(inputs.ising_2d(64, 64, b), chi, env)
+    dt = time.perf_counter() - t0
+    return {"value": len(picks) / dt, "unit": "networks/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(picks)} of the 32 networks, one per (chi, env) in turn at betas "
+                      f"{sorted(set(round(p[2], 4) for p in picks))}; {dt:.1f} s on the host"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=8, help="networks timed in the CPU oracle (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the workload's networks "
+              "are independent and would be split across GPUs, which this build does not do.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2406_09769_amd import tnapprox as T
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    nets, chis, envs = workload()
+    handles = [T.create_network(n) for n in nets]
+    slices = [n.slices for n in nets]
+    print(f"[bench] {len(nets)} networks uploaded; warmup {args.warmup}, timed steps {args.steps}",
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        T.tn_contract_approx_batch(handles, slices, chis, envs, stream=stream)
+        print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_s = []
+    rs = None
+    for i in range(args.steps):
+        rs = T.tn_contract_approx_batch(handles, slices, chis, envs, stream=stream)
+        kernel_s.append(rs[0].seconds)
+        print(f"[bench] step {i}: {rs[0].seconds * 1e3:.1f} ms in the kernel", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = len(nets) / (ms_per_step / 1e3)
+
+    flops = sum(r.flops for r in rs)
+    eig_flops = sum(r.eig_flops for r in rs)
+    ksec = sum(kernel_s) / len(kernel_s)
+    achieved = flops / ksec / 1e12
+    errs = golden_errors(rs, chis, envs)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "networks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "form": "plain FP64 (exact eigensolve), 32 networks in one persistent launch",
+        "config": {"workload": "ising2d_64x64_open_J1_h0 x 8 betas linspace(0.30,0.60,8) x chi{32,64} x env{1,2}",
+                   "networks": len(nets), "lattice": "64x64", "chi": [32, 64], "env_size": [1, 2]},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 5), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 7), "traffic": None,
+                     "kernel": "interp_kernel", "kernel_ms": round(ksec * 1e3, 3),
+                     "gemm_flops_per_launch": flops, "eig_flops_per_launch": eig_flops},
+        "accuracy": {"max_dlnZ_per_site_vs_oracle": (max(errs) if errs else None),
+                     "within_1e-8": (sum(e <= 1e-8 for e in errs) if errs else None)},
+    }
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * tnapprox.h - C ABI of the MI355X density-matrix approximate contraction.
+ *
+ * The library approximately contracts a closed tensor network to a scalar Z along
+ * a caller-given contraction path (the inputs of the paper's partitioned_contract,
+ * section 4.2: a network with its data, a partition and a path over it; the output
+ * is the contraction value, reported as ln|Z| as in the experiments of section 8).
+ *
+ * Consecutive path slices are fused env_size at a time into partitions; the path
+ * over partitions is maximally unbalanced (one partition absorbed per step). After
+ * each absorption the intermediate is compressed into an MPS (the MPS tree of the
+ * appendix on embedding trees) by the density-matrix algorithm (Algorithm
+ * density_matrix_alg with the memoised density matrices of Eq. dm_cache): every
+ * density matrix L = C R C^T is diagonalised and its leading eigenvectors, at most
+ * max_rank of them, are applied as projectors along the path.
+ *
+ * All entry points return an int status (TN_OK = 0). Nothing throws across the
+ * ABI. Host pointers are read during the call only; the caller keeps ownership.
+ * A handle must not be used by two threads at once; distinct handles may run on
+ * distinct threads and streams.
+ */
+#ifndef TNAPPROX_H
+#define TNAPPROX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TN_OK = 0,
+  TN_EINVAL = 1,    /* malformed network, path or argument (message via tn_last_error) */
+  TN_ENOMEM = 2,    /* device or host allocation failed */
+  TN_EDEVICE = 3,   /* a HIP runtime call failed, or no usable gfx950 device */
+  TN_ENUMERIC = 4,  /* an input tensor holds a non-finite value */
+  TN_EUNSUPPORTED = 5 /* valid input outside this build's limits (e.g. a density
+                         matrix larger than 128 x 128) */
+};
+
+/* One input tensor: host memory, row-major FP64, dims[order]. order 0 is a scalar. */
+typedef struct {
+  int32_t order;
+  const int64_t *dims;
+  const double *data;
+} tn_tensor;
+
+/* Edge: mode m0 of tensor t0 is contracted with mode m1 of tensor t1 (t0 != t1).
+ * Every mode of every tensor must appear in exactly one edge (closed networks). */
+typedef struct {
+  int32_t t0, m0, t1, m1;
+} tn_edge;
+
+/* Contraction path: n_slices ordered slices in CSR form. slice_ptr has n_slices+1
+ * entries; slice_vertices[slice_ptr[i] .. slice_ptr[i+1]) lists slice i's tensors.
+ * The slices must partition the tensor set. */
+typedef struct {
+  int32_t n_slices;
+  const int32_t *slice_ptr;
+  const int32_t *slice_vertices;
+} tn_path;
+
+typedef enum {
+  TN_FP64 = 0,          /* every contraction in FP64 on the FP64 matrix cores */
+  TN_SPLIT_BF16X3 = 1,  /* contractions as 3 BF16 products of hi/lo splits, FP32 accumulate */
+  TN_SPLIT_FP16X3 = 2   /* the same with FP16 splits (lo part pre-scaled) */
+} tn_precision;
+
+typedef enum {
+  TN_EIG_EXACT = 0,     /* full symmetric eigensolve of every density matrix */
+  TN_EIG_LEARNED = 1    /* MLP warm start + subspace iteration, exact solve as fallback */
+} tn_eig_mode;
+
+/* Options; pass NULL for the defaults (FP64, exact eigensolve, tau_rel = 1e-15,
+ * tau_deg = 1e-12, the null stream). */
+typedef struct {
+  int32_t precision;      /* tn_precision */
+  int32_t eig;            /* tn_eig_mode */
+  double residual_tol;    /* learned mode: relative subspace residual accepted (1e-6) */
+  double tau_rel;         /* eigenvalues <= tau_rel * w1 are dropped */
+  double tau_deg;         /* clusters with gap <= tau_deg * w1 are never split */
+  void *hip_stream;       /* hipStream_t the work is queued on (NULL = null stream) */
+} tn_options;
+
+/* Result of one contraction. log_abs = ln|Z| (natural log), sign in {-1, 0, +1};
+ * Z == 0 gives sign 0 and log_abs = -inf. */
+typedef struct {
+  double log_abs;
+  int32_t sign;
+  int32_t _pad;
+  double seconds;         /* device time of the call (HIP events) */
+  int64_t flops;          /* algorithmic flops of the executed contractions (sum 2mnk) */
+  int64_t eig_flops;      /* nominal eigensolver flops (9 n^3 per density matrix) */
+  int64_t n_eig;          /* density matrices diagonalised */
+  int64_t n_fallback;     /* keep() fallbacks (all eigenvalues below the floors) or
+                             learned-mode exact-solve fallbacks */
+  double max_residual;    /* learned mode: largest accepted subspace residual */
+} tn_result;
+
+typedef struct tn_net_s *tn_net;
+
+/* Copy a closed network to the device. Validates: t0 != t1, every mode used exactly
+ * once, dims agree across each edge, dims >= 1, data finite (TN_ENUMERIC
+ * otherwise). On success *out owns the device copy until tn_destroy. */
+int tn_create(const tn_tensor *tensors, int32_t n_tensors, const tn_edge *edges,
+              int32_t n_edges, tn_net *out);
+
+/* Approximate ln|Z| of net along path (section 4.2 with the MPS ansatz), keeping at
+ * most max_rank eigenvectors per density matrix (max_rank >= 1, env_size >= 1).
+ * Blocks until the result is on the host. Plans are cached on the handle per
+ * (path, max_rank, env_size). */
+int tn_contract_approx(tn_net net, const tn_path *path, int32_t max_rank,
+                       int32_t env_size, const tn_options *opt, tn_result *out);
+
+/* The same for n networks in one persistent launch (one workgroup per network;
+ * uneven sizes and mixed max_rank / env_size allowed). paths[i], max_ranks[i] and
+ * env_sizes[i] belong to nets[i]; outs has n entries. A handle may appear once. */
+int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths,
+                             const int32_t *max_ranks, const int32_t *env_sizes, int32_t n,
+                             const tn_options *opt, tn_result *outs);
+
+/* Structural plan for inspection and testing: writes a JSON text with, per
+ * partition, the leaf edges in order and the position of every tensor of the
+ * union network. Needs no device. *len is the buffer size on input and the
+ * length needed (including the terminating 0) on output. */
+int tn_plan_json(const int64_t *dims_flat, const int32_t *orders, int32_t n_tensors,
+                 const tn_edge *edges, int32_t n_edges, const tn_path *path,
+                 int32_t env_size, char *buf, int64_t *len);
+
+void tn_destroy(tn_net net);
+
+/* Static text for a status code. */
+const char *tn_error_string(int status);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *tn_last_error(void);
+
+/* ---------------------------------------------------------------- diagnostics
+ * Used by the kernel tests; each runs one device op of the contraction program on
+ * host data (copied in and out) and blocks. */
+
+/* Plan statistics for (path, max_rank, env_size) on net: stats[0..6] = op count,
+ * index-table entries, workspace doubles, GEMM flops (sum 2mnk), eigensolver flops
+ * (9 n^3 per density matrix), density matrices, largest density-matrix dimension. */
+int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size,
+                  int64_t *stats);
+
+/* C (M x N, row-major) = A B with A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn],
+ * through the contraction GEMM (FP64 matrix cores). lo_split sets the inner size of
+ * the two-level row/column index maps. */
+int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, int64_t sbk,
+                  int64_t sbn, double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split);
+
+/* U (n x ucols, row-major) = the kept leading eigenvectors of (L + L^T)/2 (n x n),
+ * zero columns past the kept rank, under opt's tau_rel and tau_deg (NULL: defaults).
+ * n <= 128. *n_fallback is 1 when no eigenvalue survived the rank rule. */
+int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *opt, double *U,
+                 int64_t *n_fallback);
+
+/* x <- x * 2^-e with e the frexp exponent of max|x|; returns e. */
+int tn_debug_rescale(double *x, int64_t count, int64_t *exponent);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNAPPROX_H */

@@ -23,7 +23,7 @@ import math
 
 import numpy as np
 
-from .dm import T, contract, absorb_all, plan_partition, partitions_of
+from .dm import T, contract, absorb_all, absorb_in_order, closing_order, plan_partition, partitions_of
 
 CLUSTER_FLOOR = 1e-10
 
@@ -162,14 +162,14 @@ def contract_canon(net, chi: int, env_size: int, tau_rel=1e-15, tau_deg=1e-12):
         plan = plan_partition(net, j, part, absorbed, path_index, mps, leaves)
         n = len(plan.leaves)
         if n == 0:
-            z = float(absorb_all(None, [u.t for u in plan.units]).data)
+            z = float(absorb_in_order(closing_order(plan.units)).data)
             if z == 0.0:
                 return -math.inf, 0
             acc += math.log(abs(z))
             sgn *= 1 if z > 0 else -1
             mps, leaves = [], []
         elif n <= 2:
-            root = absorb_all(None, [u.t for u in plan.units]).transpose_to(plan.leaves)
+            root = absorb_in_order(closing_order(plan.units)).transpose_to(plan.leaves)
             data, e = _scale_pow2(root.data)
             acc += e * LN2
             mps, leaves = [(T(data, root.labels), 1)], list(plan.leaf_edges)

@@ -98,6 +98,24 @@ def _result_log_size(a: T, b: T) -> float:
     return s
 
 
+def absorb_in_order(units):
+    """Contract tensors one at a time into a running intermediate, in the given order."""
+    cur = units[0]
+    for u in units[1:]:
+        cur = contract(cur, u)
+    return cur
+
+
+def closing_order(units):
+    """The partition's tensors sorted for a sweep along the old leaf positions.
+
+    Used when everything of a partition step is contracted at once (at most two
+    new leaves): a sweep in position order keeps the intermediate as small as the
+    boundary, whereas a greedy order can leave a whole row of bonds open.
+    """
+    return [u.t for u in sorted(units, key=lambda u: u.sweep)]
+
+
 def absorb_all(start, units):
     """Contract a list of tensors one at a time into a running intermediate.
 
@@ -164,6 +182,7 @@ class Unit:
     kind: str          # 'mps', 'site' or 'id'
     ref: int           # mps: old own-leaf position (1-based); site: vertex id; id: position
     order: int = 0     # tie-break order (mps first, then sites in path order, then ids)
+    sweep: tuple = ()  # order of the closing sweep: (old position or anchor, kind, path index)
 
 
 @dataclass
@@ -253,13 +272,14 @@ def plan_partition(net, j, part, absorbed, path_index, mps_units, old_leaves):
     # union network units
     units = []
     for (t, own) in mps_units:
-        units.append(Unit(t, 'mps', own, 0))
+        units.append(Unit(t, 'mps', own, 0, (own, 0, 0)))
     for t in order_p:
         a = net.tensors[t]
         labs = [None] * a.ndim
         for (e, m, _) in inc[t]:
             labs[m] = ('e', e)
-        units.append(Unit(T(a, tuple(labs)), 'site', t, 1 + path_index[t]))
+        units.append(Unit(T(a, tuple(labs)), 'site', t, 1 + path_index[t],
+                          (anchor[t], 1, path_index[t])))
 
     if n == 0:
         return PartitionPlan([], [], [], units, [(u.kind, u.ref, 0) for u in units])
@@ -307,7 +327,7 @@ def plan_partition(net, j, part, absorbed, path_index, mps_units, old_leaves):
             ut = units[owner].t
             units[owner].t = T(ut.data, tuple(s if l == lab else l for l in ut.labels))
             d = ut.dim(lab)
-            units.append(Unit(T(np.eye(d), (s, lab)), 'id', k, big + k))
+            units.append(Unit(T(np.eye(d), (s, lab)), 'id', k, big + k, (math.inf, 2, k)))
             pos.append(k)
 
     groups = [[] for _ in range(n)]
@@ -381,7 +401,7 @@ def contract_approx(net, chi: int, env_size: int, tau_rel=TAU_REL, tau_deg=TAU_D
         n = len(plan.leaves)
         units = plan.units
         if n == 0:
-            z = absorb_all(None, [u.t for u in units])
+            z = absorb_in_order(closing_order(units))
             val = float(z.data)
             if val == 0.0:
                 return -math.inf, 0
@@ -389,7 +409,7 @@ def contract_approx(net, chi: int, env_size: int, tau_rel=TAU_REL, tau_deg=TAU_D
             sgn *= 1 if val > 0 else -1
             mps, leaves = [], []
         elif n <= 2:
-            root = absorb_all(None, [u.t for u in units]).transpose_to(plan.leaves)
+            root = absorb_in_order(closing_order(units)).transpose_to(plan.leaves)
             root, e = rescale(root)
             acc += e * LN2
             if not np.any(root.data):

@@ -1,0 +1,476 @@
+// api.cpp - the C ABI (include/tnapprox.h): handles, plan cache, device buffers, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "planner.hpp"
+#include "tnapprox.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) return fail(TN_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevPlan {
+  tn::Plan plan;
+  tn::Op *d_ops = nullptr;
+  int32_t *d_tab = nullptr;
+  ~DevPlan() {
+    if (d_ops) (void)hipFree(d_ops);
+    if (d_tab) (void)hipFree(d_tab);
+  }
+};
+
+using PlanKey = std::tuple<std::vector<std::vector<int32_t>>, int32_t, int32_t>;
+
+int check_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(TN_EDEVICE, "no HIP device visible");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(TN_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  return TN_OK;
+}
+
+int read_path(const tn_path *path, int32_t nt, std::vector<std::vector<int32_t>> &slices) {
+  if (!path || path->n_slices < 1 || !path->slice_ptr || !path->slice_vertices)
+    return fail(TN_EINVAL, "path is empty or has null arrays");
+  slices.assign(path->n_slices, {});
+  if (path->slice_ptr[0] != 0) return fail(TN_EINVAL, "slice_ptr[0] must be 0");
+  for (int32_t s = 0; s < path->n_slices; ++s) {
+    int32_t b = path->slice_ptr[s], e = path->slice_ptr[s + 1];
+    if (e < b || e > nt) return fail(TN_EINVAL, "slice_ptr is not non-decreasing within the tensor count");
+    slices[s].assign(path->slice_vertices + b, path->slice_vertices + e);
+  }
+  if (path->slice_ptr[path->n_slices] != nt) return fail(TN_EINVAL, "slices do not list every tensor exactly once");
+  return TN_OK;
+}
+
+}  // namespace
+
+struct tn_net_s {
+  tn::Graph g;
+  double *d_const = nullptr;
+  double *d_ws = nullptr;
+  int64_t ws_cap = 0;
+  tn::NetScalars *d_sc = nullptr;
+  std::map<PlanKey, std::unique_ptr<DevPlan>> plans;
+  ~tn_net_s() {
+    plans.clear();
+    if (d_const) (void)hipFree(d_const);
+    if (d_ws) (void)hipFree(d_ws);
+    if (d_sc) (void)hipFree(d_sc);
+  }
+};
+
+namespace {
+
+int get_plan(tn_net net, const std::vector<std::vector<int32_t>> &slices, int32_t chi, int32_t env,
+             DevPlan **out) {
+  PlanKey key{slices, chi, env};
+  auto it = net->plans.find(key);
+  if (it != net->plans.end()) { *out = it->second.get(); return TN_OK; }
+  auto dp = std::make_unique<DevPlan>();
+  tn::PlanArgs pa;
+  pa.slices = slices;
+  pa.chi = chi;
+  pa.env = env;
+  bool unsup = false;
+  std::string err = tn::make_plan(net->g, pa, dp->plan, &unsup);
+  if (!err.empty()) return fail(unsup ? TN_EUNSUPPORTED : TN_EINVAL, err);
+  size_t ob = dp->plan.ops.size() * sizeof(tn::Op), tb = std::max<size_t>(1, dp->plan.tables.size()) * 4;
+  if (hipMalloc(&dp->d_ops, std::max<size_t>(ob, 64)) != hipSuccess ||
+      hipMalloc(&dp->d_tab, tb) != hipSuccess)
+    return fail(TN_ENOMEM, "device allocation for the plan failed");
+  if (ob) HIP_TRY(hipMemcpy(dp->d_ops, dp->plan.ops.data(), ob, hipMemcpyHostToDevice));
+  if (!dp->plan.tables.empty())
+    HIP_TRY(hipMemcpy(dp->d_tab, dp->plan.tables.data(), dp->plan.tables.size() * 4, hipMemcpyHostToDevice));
+  *out = dp.get();
+  net->plans.emplace(std::move(key), std::move(dp));
+  return TN_OK;
+}
+
+int ensure_ws(tn_net net, int64_t doubles) {
+  doubles = std::max<int64_t>(doubles, 32);
+  if (net->ws_cap >= doubles) return TN_OK;
+  if (net->d_ws) (void)hipFree(net->d_ws);
+  net->d_ws = nullptr;
+  net->ws_cap = 0;
+  if (hipMalloc(&net->d_ws, size_t(doubles) * 8) != hipSuccess)
+    return fail(TN_ENOMEM, "workspace allocation of " + std::to_string(doubles * 8) + " bytes failed");
+  net->ws_cap = doubles;
+  return TN_OK;
+}
+
+tn_options defaults() {
+  tn_options o;
+  std::memset(&o, 0, sizeof(o));
+  o.precision = TN_FP64;
+  o.eig = TN_EIG_EXACT;
+  o.residual_tol = 1e-6;
+  o.tau_rel = 1e-15;
+  o.tau_deg = 1e-12;
+  o.hip_stream = nullptr;
+  return o;
+}
+
+// Run a list of prepared networks in one interpreter launch.
+int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &plans, const tn_options &o,
+              double *seconds, std::vector<tn::NetScalars> &sc_out) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(o.hip_stream);
+  const size_t n = nets.size();
+  std::vector<tn::NetDev> nd(n);
+  tn::NetScalars init{};
+  init.sign = 1;
+  for (size_t i = 0; i < n; ++i) {
+    HIP_TRY(hipMemcpyAsync(nets[i]->d_sc, &init, sizeof(init), hipMemcpyHostToDevice, st));
+    nd[i].ops = plans[i]->d_ops;
+    nd[i].n_ops = int64_t(plans[i]->plan.ops.size());
+    nd[i].tab = plans[i]->d_tab;
+    nd[i].ws = nets[i]->d_ws;
+    nd[i].cst = nets[i]->d_const;
+    nd[i].sc = nets[i]->d_sc;
+  }
+  tn::NetDev *d_nd = nullptr;
+  if (hipMalloc(&d_nd, n * sizeof(tn::NetDev)) != hipSuccess) return fail(TN_ENOMEM, "launch descriptor allocation failed");
+  std::unique_ptr<tn::NetDev, void (*)(tn::NetDev *)> guard(d_nd, [](tn::NetDev *p) { (void)hipFree(p); });
+  HIP_TRY(hipMemcpyAsync(d_nd, nd.data(), n * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
+  HIP_TRY(hipEventRecord(e0, st));
+  HIP_TRY(tn::launch_interp(d_nd, int(n), kp, st));
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *seconds = ms * 1e-3;
+  sc_out.resize(n);
+  for (size_t i = 0; i < n; ++i)
+    HIP_TRY(hipMemcpy(&sc_out[i], nets[i]->d_sc, sizeof(tn::NetScalars), hipMemcpyDeviceToHost));
+  return TN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tn_error_string(int status) {
+  switch (status) {
+    case TN_OK: return "ok";
+    case TN_EINVAL: return "invalid argument";
+    case TN_ENOMEM: return "out of memory";
+    case TN_EDEVICE: return "device error";
+    case TN_ENUMERIC: return "non-finite input";
+    case TN_EUNSUPPORTED: return "unsupported by this build";
+    default: return "unknown status";
+  }
+}
+
+const char *tn_last_error(void) { return g_err.c_str(); }
+
+int tn_create(const tn_tensor *tensors, int32_t n_tensors, const tn_edge *edges, int32_t n_edges, tn_net *out) {
+  g_err.clear();
+  if (!out) return fail(TN_EINVAL, "out is null");
+  *out = nullptr;
+  if (!tensors || n_tensors < 1) return fail(TN_EINVAL, "no tensors");
+  if (n_edges > 0 && !edges) return fail(TN_EINVAL, "edges is null");
+  std::vector<const int64_t *> dims(n_tensors);
+  std::vector<int32_t> orders(n_tensors);
+  for (int32_t t = 0; t < n_tensors; ++t) {
+    orders[t] = tensors[t].order;
+    dims[t] = tensors[t].dims;
+    if (tensors[t].order > 0 && !tensors[t].dims) return fail(TN_EINVAL, "tensor dims is null");
+    if (!tensors[t].data) return fail(TN_EINVAL, "tensor data is null");
+  }
+  std::vector<int32_t> e4(4 * size_t(std::max(n_edges, 0)));
+  for (int32_t e = 0; e < n_edges; ++e) {
+    e4[4 * e] = edges[e].t0; e4[4 * e + 1] = edges[e].m0; e4[4 * e + 2] = edges[e].t1; e4[4 * e + 3] = edges[e].m1;
+  }
+  auto net = std::make_unique<tn_net_s>();
+  std::string err = tn::build_graph(dims.data(), orders.data(), n_tensors, e4.data(), n_edges, net->g);
+  if (!err.empty()) return fail(TN_EINVAL, err);
+  std::vector<double> host(std::max<int64_t>(net->g.const_size, 1), 0.0);
+  for (int32_t t = 0; t < n_tensors; ++t) {
+    int64_t size = 1;
+    for (int64_t d : net->g.dims[t]) size *= d;
+    for (int64_t i = 0; i < size; ++i) {
+      double v = tensors[t].data[i];
+      if (!std::isfinite(v)) return fail(TN_ENUMERIC, "tensor " + std::to_string(t) + " holds a non-finite value");
+      host[net->g.const_off[t] + i] = v;
+    }
+  }
+  int rc = check_device();
+  if (rc != TN_OK) return rc;
+  if (hipMalloc(&net->d_const, host.size() * 8) != hipSuccess) return fail(TN_ENOMEM, "constant area allocation failed");
+  if (hipMalloc(&net->d_sc, sizeof(tn::NetScalars)) != hipSuccess) return fail(TN_ENOMEM, "scalar allocation failed");
+  HIP_TRY(hipMemcpy(net->d_const, host.data(), host.size() * 8, hipMemcpyHostToDevice));
+  *out = net.release();
+  return TN_OK;
+}
+
+void tn_destroy(tn_net net) { delete net; }
+
+int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int32_t *max_ranks,
+                             const int32_t *env_sizes, int32_t n, const tn_options *opt, tn_result *outs) {
+  g_err.clear();
+  if (!nets || !paths || !outs || !max_ranks || !env_sizes || n < 1) return fail(TN_EINVAL, "null arrays or empty batch");
+  for (int32_t i = 0; i < n; ++i) {
+    if (max_ranks[i] < 1) return fail(TN_EINVAL, "max_rank must be >= 1");
+    if (env_sizes[i] < 1) return fail(TN_EINVAL, "env_size must be >= 1");
+  }
+  tn_options o = opt ? *opt : defaults();
+  if (o.precision != TN_FP64) return fail(TN_EUNSUPPORTED, "precision form not available in this build");
+  if (o.eig != TN_EIG_EXACT) return fail(TN_EUNSUPPORTED, "learned eigensolve not available in this build");
+  if (!(o.tau_rel >= 0) || !(o.tau_deg >= 0)) return fail(TN_EINVAL, "tau_rel and tau_deg must be >= 0");
+  std::vector<tn_net> v(nets, nets + n);
+  std::vector<DevPlan *> plans(n);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!v[i]) return fail(TN_EINVAL, "null network handle");
+    for (int32_t j = 0; j < i; ++j)
+      if (v[j] == v[i]) return fail(TN_EINVAL, "a handle appears twice in one batch");
+    std::vector<std::vector<int32_t>> slices;
+    int rc = read_path(&paths[i], v[i]->g.nt, slices);
+    if (rc != TN_OK) return rc;
+    rc = get_plan(v[i], slices, max_ranks[i], env_sizes[i], &plans[i]);
+    if (rc != TN_OK) return rc;
+    rc = ensure_ws(v[i], plans[i]->plan.ws_size);
+    if (rc != TN_OK) return rc;
+  }
+  double secs = 0;
+  std::vector<tn::NetScalars> sc;
+  int rc = run_batch(v, plans, o, &secs, sc);
+  if (rc != TN_OK) return rc;
+  for (int32_t i = 0; i < n; ++i) {
+    tn_result &r = outs[i];
+    std::memset(&r, 0, sizeof(r));
+    if (sc[i].zero) {
+      r.log_abs = -std::numeric_limits<double>::infinity();
+      r.sign = 0;
+    } else {
+      r.log_abs = double(sc[i].exp_sum) * std::log(2.0) + sc[i].log_sum;
+      r.sign = int32_t(sc[i].sign);
+    }
+    r.seconds = secs;
+    r.flops = plans[i]->plan.flops;
+    r.eig_flops = plans[i]->plan.eig_flops;
+    r.n_eig = plans[i]->plan.n_eig;
+    r.n_fallback = sc[i].n_fallback;
+    r.max_residual = sc[i].max_resid;
+  }
+  return TN_OK;
+}
+
+int tn_contract_approx(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size,
+                       const tn_options *opt, tn_result *out) {
+  return tn_contract_approx_batch(&net, path, &max_rank, &env_size, 1, opt, out);
+}
+
+int tn_plan_json(const int64_t *dims_flat, const int32_t *orders, int32_t n_tensors, const tn_edge *edges,
+                 int32_t n_edges, const tn_path *path, int32_t env_size, char *buf, int64_t *len) {
+  g_err.clear();
+  if (!orders || !len || n_tensors < 1) return fail(TN_EINVAL, "null arguments");
+  std::vector<const int64_t *> dims(n_tensors);
+  int64_t off = 0;
+  for (int32_t t = 0; t < n_tensors; ++t) {
+    dims[t] = dims_flat + off;
+    off += std::max(orders[t], 0);
+  }
+  std::vector<int32_t> e4(4 * size_t(std::max(n_edges, 0)));
+  for (int32_t e = 0; e < n_edges; ++e) {
+    e4[4 * e] = edges[e].t0; e4[4 * e + 1] = edges[e].m0; e4[4 * e + 2] = edges[e].t1; e4[4 * e + 3] = edges[e].m1;
+  }
+  tn::Graph g;
+  std::string err = tn::build_graph(dims.data(), orders, n_tensors, e4.data(), n_edges, g);
+  if (!err.empty()) return fail(TN_EINVAL, err);
+  std::vector<std::vector<int32_t>> slices;
+  int rc = read_path(path, n_tensors, slices);
+  if (rc != TN_OK) return rc;
+  tn::PlanArgs pa;
+  pa.slices = slices;
+  pa.chi = 1;
+  pa.env = env_size;
+  tn::Plan plan;
+  bool unsup = false;
+  err = tn::make_plan(g, pa, plan, &unsup);
+  if (!err.empty()) return fail(unsup ? TN_EUNSUPPORTED : TN_EINVAL, err);
+  int64_t need = int64_t(plan.plan_json.size()) + 1;
+  if (buf && *len >= need) std::memcpy(buf, plan.plan_json.c_str(), size_t(need));
+  int64_t have = *len;
+  *len = need;
+  if (buf && have < need) return fail(TN_EINVAL, "buffer too small");
+  return TN_OK;
+}
+
+// ---------------------------------------------------------------- diagnostics
+
+int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size, int64_t *stats) {
+  g_err.clear();
+  if (!net || !stats) return fail(TN_EINVAL, "null arguments");
+  std::vector<std::vector<int32_t>> slices;
+  int rc = read_path(path, net->g.nt, slices);
+  if (rc != TN_OK) return rc;
+  DevPlan *dp = nullptr;
+  rc = get_plan(net, slices, max_rank, env_size, &dp);
+  if (rc != TN_OK) return rc;
+  stats[0] = int64_t(dp->plan.ops.size());
+  stats[1] = int64_t(dp->plan.tables.size());
+  stats[2] = dp->plan.ws_size;
+  stats[3] = dp->plan.flops;
+  stats[4] = dp->plan.eig_flops;
+  stats[5] = dp->plan.n_eig;
+  stats[6] = dp->plan.max_eig_dim;
+  return TN_OK;
+}
+
+// Run single device ops on host data through the same interpreter (kernel tests).
+static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t> &tab, std::vector<double> &ws,
+                      const std::vector<double> &cst, const tn::KeepParams &kp, tn::NetScalars *sc_out) {
+  int rc = check_device();
+  if (rc != TN_OK) return rc;
+  tn::Op *d_ops = nullptr;
+  int32_t *d_tab = nullptr;
+  double *d_ws = nullptr, *d_cst = nullptr;
+  tn::NetScalars *d_sc = nullptr;
+  tn::NetDev *d_nd = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(d_ops); (void)hipFree(d_tab); (void)hipFree(d_ws); (void)hipFree(d_cst);
+    (void)hipFree(d_sc); (void)hipFree(d_nd);
+  };
+  if (hipMalloc(&d_ops, ops.size() * sizeof(tn::Op)) != hipSuccess ||
+      hipMalloc(&d_tab, std::max<size_t>(tab.size(), 1) * 4) != hipSuccess ||
+      hipMalloc(&d_ws, std::max<size_t>(ws.size(), 1) * 8) != hipSuccess ||
+      hipMalloc(&d_cst, std::max<size_t>(cst.size(), 1) * 8) != hipSuccess ||
+      hipMalloc(&d_sc, sizeof(tn::NetScalars)) != hipSuccess ||
+      hipMalloc(&d_nd, sizeof(tn::NetDev)) != hipSuccess) {
+    cleanup();
+    return fail(TN_ENOMEM, "diagnostic allocation failed");
+  }
+  tn::NetScalars init{};
+  init.sign = 1;
+  tn::NetDev nd{d_ops, int64_t(ops.size()), d_tab, d_ws, d_cst, d_sc};
+  hipError_t e = hipMemcpy(d_ops, ops.data(), ops.size() * sizeof(tn::Op), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !tab.empty()) e = hipMemcpy(d_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !ws.empty()) e = hipMemcpy(d_ws, ws.data(), ws.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !cst.empty()) e = hipMemcpy(d_cst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_sc, &init, sizeof(init), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_nd, &nd, sizeof(nd), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = tn::launch_interp(d_nd, 1, kp, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess && !ws.empty()) e = hipMemcpy(ws.data(), d_ws, ws.size() * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && sc_out) e = hipMemcpy(sc_out, d_sc, sizeof(tn::NetScalars), hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) return fail(TN_EDEVICE, std::string("diagnostic run: ") + hipGetErrorString(e));
+  return TN_OK;
+}
+
+int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, int64_t sbk, int64_t sbn,
+                  double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split) {
+  g_err.clear();
+  if (!A || !B || !C || M < 1 || N < 1 || K < 1) return fail(TN_EINVAL, "bad gemm arguments");
+  if (lo_split < 1) lo_split = 1;
+  std::vector<int32_t> tab;
+  auto push_map = [&](int32_t n, int64_t stride, tn::IdxMap &m) {
+    int32_t lo = std::min(lo_split, n);
+    int32_t nh = (n + lo - 1) / lo;
+    m.hi = int64_t(tab.size());
+    for (int32_t h = 0; h < nh; ++h) tab.push_back(int32_t(int64_t(h) * lo * stride));
+    m.lo = int64_t(tab.size());
+    for (int32_t l = 0; l < lo; ++l) tab.push_back(int32_t(l * stride));
+    m.lo_n = lo;
+    m.n = n;
+  };
+  int64_t maxa = (M - 1) * sam + (K - 1) * sak + 1, maxb = (K - 1) * sbk + (N - 1) * sbn + 1;
+  tn::Op op{};
+  op.kind = tn::OP_GEMM;
+  op.flags = tn::F_A_CONST | tn::F_B_CONST | (sak == 1 ? tn::F_A_KFAST : 0) | (sbn == 1 ? tn::F_B_NFAST : 0);
+  push_map(M, sam, op.am);
+  push_map(N, sbn, op.bn);
+  op.K = K;
+  op.ak = int32_t(tab.size());
+  for (int32_t k = 0; k < K; ++k) tab.push_back(int32_t(k * sak));
+  op.bk = int32_t(tab.size());
+  for (int32_t k = 0; k < K; ++k) tab.push_back(int32_t(k * sbk));
+  std::vector<double> cst(A, A + maxa);
+  op.a = 0;
+  op.b = (maxa + 31) / 32 * 32;
+  cst.resize(op.b, 0.0);
+  cst.insert(cst.end(), B, B + maxb);
+  op.c = 0;
+  std::vector<double> ws(int64_t(M) * N, 0.0);
+  tn::KeepParams kp{1e-15, 1e-12, tn::kClusterFloor};
+  int rc = run_single({op}, tab, ws, cst, kp, nullptr);
+  if (rc != TN_OK) return rc;
+  std::memcpy(C, ws.data(), ws.size() * 8);
+  return TN_OK;
+}
+
+int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *opt, double *U, int64_t *n_fallback) {
+  g_err.clear();
+  if (!L || !U || n < 1 || n > tn::kMaxEigDim || ucols < 1 || ucols > n) return fail(TN_EINVAL, "bad eig arguments");
+  tn_options o = opt ? *opt : defaults();
+  const int64_t np = n + (n & 1);
+  tn::Op op{};
+  op.kind = tn::OP_EIG;
+  op.count = n;
+  op.K = ucols;
+  op.a = 0;
+  int64_t lsz = (int64_t(n) * n + 31) / 32 * 32;
+  op.c = lsz;
+  int64_t usz = (int64_t(n) * ucols + 31) / 32 * 32;
+  op.b = lsz + usz;
+  if (2 * np * np + 4 * np + 16 > 20000) op.flags |= tn::F_V_GLOBAL;
+  std::vector<double> ws(lsz + usz + np * np, 0.0);
+  std::memcpy(ws.data(), L, size_t(n) * n * 8);
+  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
+  tn::NetScalars sc{};
+  int rc = run_single({op}, {}, ws, {}, kp, &sc);
+  if (rc != TN_OK) return rc;
+  std::memcpy(U, ws.data() + lsz, size_t(n) * ucols * 8);
+  if (n_fallback) *n_fallback = sc.n_fallback;
+  return TN_OK;
+}
+
+int tn_debug_rescale(double *x, int64_t count, int64_t *exponent) {
+  g_err.clear();
+  if (!x || count < 1) return fail(TN_EINVAL, "bad rescale arguments");
+  tn::Op op{};
+  op.kind = tn::OP_RESCALE;
+  op.flags = tn::F_ACCUM;
+  op.c = 0;
+  op.count = count;
+  std::vector<double> ws(x, x + count);
+  tn::KeepParams kp{1e-15, 1e-12, tn::kClusterFloor};
+  tn::NetScalars sc{};
+  int rc = run_single({op}, {}, ws, {}, kp, &sc);
+  if (rc != TN_OK) return rc;
+  std::memcpy(x, ws.data(), size_t(count) * 8);
+  if (exponent) *exponent = sc.exp_sum;
+  return TN_OK;
+}
+
+}  // extern "C"

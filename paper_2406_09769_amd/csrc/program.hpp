@@ -1,0 +1,65 @@
+// program.hpp - the device program a plan compiles to.
+//
+// A plan turns one (network, path, max_rank, env_size) into a flat list of Ops
+// over one network's workspace. The same Op list runs on the device either in the
+// persistent interpreter (one workgroup walks every op of one network) or op by
+// op with grid-wide launches. Offsets are in elements; int32 index tables live in
+// one table pool per plan.
+#pragma once
+#include <stdint.h>
+
+namespace tn {
+
+enum OpKind : int32_t {
+  OP_GEMM = 1,     // C[m*N+n] = sum_k A[am(m)+ak(k)] * B[bk(k)+bn(n)]
+  OP_EIG = 2,      // U = kept leading eigenvectors of sym(L), zero-padded to ucols
+  OP_RESCALE = 3,  // x *= 2^-e, e = frexp exponent of max|x|; optionally sum e
+  OP_SCALAR = 4,   // z = x[0]: add ln|z| and sign(z) to the result
+  OP_IDENT = 5,    // x = identity (dim x dim)
+};
+
+enum OpFlags : int32_t {
+  F_A_CONST = 1,      // A operand lives in the network's input (constant) area
+  F_B_CONST = 2,      // B operand lives in the constant area
+  F_ACCUM = 4,        // OP_RESCALE: add the exponent to the log accumulator
+  F_A_KFAST = 8,      // load A tiles with k varying fastest across threads
+  F_B_NFAST = 16,     // load B tiles with n varying fastest across threads
+  F_V_GLOBAL = 32,    // OP_EIG: eigenvector accumulator lives in the workspace
+};
+
+// A two-level index map over a row-major multi-index: off(i) = hi[i / lo_n] + lo[i % lo_n]
+struct IdxMap {
+  int64_t hi;     // table offset of the outer part
+  int64_t lo;     // table offset of the inner part
+  int32_t lo_n;   // size of the inner part
+  int32_t n;      // total extent
+};
+
+struct Op {
+  int32_t kind;
+  int32_t flags;
+  int64_t c;        // GEMM/EIG/IDENT output offset; RESCALE/SCALAR operand offset
+  int64_t a;        // GEMM A; EIG input L
+  int64_t b;        // GEMM B; EIG scratch (V) when F_V_GLOBAL
+  int64_t count;    // RESCALE element count; EIG: matrix dim n; IDENT: dim
+  int32_t K;        // GEMM contraction extent; EIG: ucols (static kept columns)
+  int32_t ak;       // GEMM: table offset of A's k offsets
+  int32_t bk;       // GEMM: table offset of B's k offsets
+  int32_t pad;
+  IdxMap am;        // GEMM: A row map (extent M)
+  IdxMap bn;        // GEMM: B column map (extent N)
+};
+
+// Scalars each network accumulates on the device.
+struct NetScalars {
+  double log_sum;     // sum of ln|z| terms
+  double max_resid;   // learned eigensolve: largest accepted residual
+  long long exp_sum;  // sum of power-of-two exponents (exact)
+  long long sign;     // +1 / -1
+  long long zero;     // 1 once Z is exactly zero
+  long long n_fallback;
+  long long n_learned;
+  long long pad;
+};
+
+}  // namespace tn

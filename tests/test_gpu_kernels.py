@@ -1,0 +1,92 @@
+"""Device kernels through the C-ABI diagnostics, against plain numpy FP64.
+
+GEMM: the contraction GEMM (FP64 matrix cores, index-table gathers) on ragged,
+strided and transposed operands and two-level index maps.
+Eigensolve: kept subspace (projector) and rank versus numpy's eigh and the
+oracle's keep rule. Rescale: exact powers of two."""
+import numpy as np
+import pytest
+
+from oracle import dm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2406_09769_amd import tnapprox
+    return tnapprox
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (16, 16, 4), (64, 64, 16), (65, 63, 17), (200, 130, 70),
+                                   (3, 257, 129), (128, 128, 256)])
+def test_gemm_matches_numpy(T, M, N, K):
+    rng = np.random.default_rng(M * 1000 + N + K)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    C = T.tn_debug_gemm(A, B)
+    ref = A @ B
+    assert np.max(np.abs(C - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * max(1, K) ** 0.5
+
+
+@pytest.mark.parametrize("lo", [1, 7, 64])
+def test_gemm_strided_and_two_level_maps(T, lo):
+    rng = np.random.default_rng(lo)
+    A = rng.standard_normal((90, 37)).T          # A is a transposed view (m stride 1)
+    B = rng.standard_normal((51, 90)).T[:, ::1]  # B(k, n) with n stride 90
+    C = T.tn_debug_gemm(A, B, lo_split=lo)
+    assert np.allclose(C, A @ B, rtol=0, atol=1e-12)
+
+
+def _psd(n, spectrum, seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
+    return q @ np.diag(spectrum) @ q.T
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 16, 33, 64, 97, 98, 99, 127, 128])
+def test_eig_subspace_and_rank_match_oracle(T, n):
+    rng = np.random.default_rng(n)
+    w = np.sort(np.exp(-rng.uniform(0, 30, n)))[::-1]
+    L = _psd(n, w, n + 1)
+    ucols = max(1, n // 2)
+    U, fb = T.tn_debug_eig(L, ucols)
+    Uo, wo, k, _ = dm.keep(L, ucols)
+    kept = int(np.sum(np.any(U != 0.0, axis=0)))
+    assert kept == k and fb == 0
+    assert np.all(U[:, k:] == 0.0)
+    Uk = U[:, :k]
+    assert np.allclose(Uk.T @ Uk, np.eye(k), atol=1e-12)
+    assert np.max(np.abs(Uk @ Uk.T - Uo @ Uo.T)) < 1e-9
+
+
+def test_eig_does_not_split_degenerate_cluster(T):
+    w = np.array([1.0, 0.5, 0.25, 0.25, 0.1, 0.0])
+    L = _psd(6, w, 3)
+    U, _ = T.tn_debug_eig(L, 3)
+    assert int(np.sum(np.any(U != 0.0, axis=0))) == 2
+
+
+def test_eig_zero_padding_is_invisible(T):
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((20, 20))
+    L = a @ a.T
+    Lp = np.zeros((40, 40))
+    Lp[:20, :20] = L
+    U, _ = T.tn_debug_eig(Lp, 16)
+    k = int(np.sum(np.any(U != 0.0, axis=0)))
+    assert k == dm.keep(L, 16)[2]
+    assert np.all(U[20:, :] == 0.0)
+
+
+def test_eig_zero_matrix_falls_back(T):
+    U, fb = T.tn_debug_eig(np.zeros((8, 8)), 4)
+    assert fb == 1
+
+
+@pytest.mark.parametrize("scale", [1.0, 3e-200, 7e250, -2.5])
+def test_rescale_is_exact_power_of_two(T, scale):
+    x = np.random.default_rng(1).standard_normal(1000) * scale
+    y, e = T.tn_debug_rescale(x)
+    _, want = np.frexp(np.max(np.abs(x)))
+    assert e == want
+    assert np.array_equal(y, np.ldexp(x, -e))

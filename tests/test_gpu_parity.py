@@ -1,0 +1,144 @@
+"""GPU path (C-ABI, plain FP64) against the CPU oracle on the same seeded inputs.
+
+Bar: |ln|Z|_gpu - ln|Z|_oracle| / N <= 1e-10 per site and equal signs."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2406_09769_amd import inputs
+from oracle import dm, exact
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2406_09769_amd import tnapprox
+    return tnapprox
+
+
+def gpu(T, net, chi, env, **kw):
+    h = T.create_network(net)
+    return T.tn_contract_approx(h, net.slices, chi, env, **kw)
+
+
+def check(T, net, chi, env):
+    r = gpu(T, net, chi, env)
+    v, s = dm.contract_approx(net, chi, env)
+    print(f"{net.name} chi={chi} env={env}: gpu {r.log_abs!r} oracle {v!r} diff/N {(r.log_abs - v) / net.n_sites:.3e}",
+          flush=True)
+    assert r.sign == s
+    assert abs(r.log_abs - v) / net.n_sites <= TOL
+    return r
+
+
+@pytest.mark.parametrize("chi", [4, 16])
+def test_w1_6x6(T, chi):
+    net = inputs.ising_2d(6, 6, 0.44)
+    r = check(T, net, chi, 1)
+    if chi == 16:   # full bond dimension: exact
+        assert abs(r.log_abs - exact.tm_2d(6, 6, 0.44)) / 36 <= 1e-13
+
+
+@pytest.mark.parametrize("env", [1, 2, 3])
+def test_2d_env_sizes(T, env):
+    check(T, inputs.ising_2d(9, 8, 0.5), 6, env)
+
+
+def test_narrow_strip_exact_at_chi64(T):
+    net = inputs.ising_2d(64, 12, 0.44)
+    r = check(T, net, 64, 1)
+    assert abs(r.log_abs - exact.tm_2d(64, 12, 0.44)) / net.n_sites <= 1e-11
+
+
+def test_3d_small(T):
+    check(T, inputs.ising_3d(3, 3, 3, 0.25), 8, 1)
+    net = inputs.ising_3d(4, 3, 3, 0.2217)
+    r = check(T, net, 32, 1)
+    assert abs(r.log_abs - exact.tm_3d(4, 3, 3, 0.2217)) / net.n_sites <= 1e-11
+
+
+@pytest.mark.parametrize("seed", [101, 102])
+def test_rrg_signed(T, seed):
+    check(T, inputs.ising_rrg(30, 1.0, seed=seed), 8, 1)
+
+
+def test_csp(T):
+    rng = np.random.default_rng(77)
+    net = inputs.csp_network(24, inputs.random_3sat(24, 60, rng))
+    check(T, net, 8, 1)
+
+
+def test_batch_of_betas_one_launch(T):
+    nets = [inputs.ising_2d(10, 10, b) for b in inputs.w2_betas()]
+    hs = [T.create_network(n) for n in nets]
+    rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], 8, 1)
+    for net, r in zip(nets, rs):
+        v, s = dm.contract_approx(net, 8, 1)
+        assert r.sign == s and abs(r.log_abs - v) / net.n_sites <= TOL
+
+
+def test_uneven_batch_one_launch(T):
+    nets = [inputs.ising_rrg(n, 1.0, seed=200 + n) for n in (12, 20, 34)]
+    nets.append(inputs.ising_2d(5, 7, 0.4))
+    hs = [T.create_network(n) for n in nets]
+    rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], 6, 1)
+    for net, r in zip(nets, rs):
+        v, s = dm.contract_approx(net, 6, 1)
+        assert r.sign == s and abs(r.log_abs - v) / net.n_sites <= TOL
+
+
+def test_zero_and_negative_networks(T):
+    net = inputs.ising_2d(5, 5, 0.44)
+    net.tensors[12] = np.zeros_like(net.tensors[12])
+    r = gpu(T, net, 4, 1)
+    assert r.sign == 0 and r.log_abs == -math.inf
+    net = inputs.ising_2d(5, 5, 0.44)
+    net.tensors[3] = -net.tensors[3]
+    r = gpu(T, net, 4, 1)
+    v, s = dm.contract_approx(net, 4, 1)
+    assert r.sign == -1 == s and abs(r.log_abs - v) <= 1e-10
+
+
+def test_degenerate_networks(T):
+    # a single scalar tensor; two tensors joined by one bond; a 1 x 2 lattice
+    h = T.tn_create([np.array(3.5)], [])
+    r = T.tn_contract_approx(h, [[0]], 4, 1)
+    assert r.sign == 1 and abs(r.log_abs - math.log(3.5)) < 1e-15
+    a, b = np.array([1.0, -2.0]), np.array([3.0, 0.5])
+    h = T.tn_create([a, b], [(0, 0, 1, 0)])
+    r = T.tn_contract_approx(h, [[0], [1]], 1, 1)
+    assert r.sign == 1 and abs(r.log_abs - math.log(2.0)) < 1e-15
+    net = inputs.ising_2d(1, 2, 0.44)
+    r = gpu(T, net, 2, 1)
+    assert abs(r.log_abs - exact.tm_2d(1, 2, 0.44)) < 1e-14
+
+
+def test_repeat_calls_are_deterministic(T):
+    net = inputs.ising_2d(12, 12, 0.44)
+    h = T.create_network(net)
+    a = T.tn_contract_approx(h, net.slices, 8, 2)
+    b = T.tn_contract_approx(h, net.slices, 8, 2)
+    assert a.log_abs == b.log_abs
+
+
+def test_w2_full_size_against_golden(T):
+    """64x64 lattices at the 8 betas, chi 32, env 1 and 2, one launch per (chi, env);
+    expected values written by tests/golden/make_golden.py from the oracle."""
+    path = os.path.join(HERE, "golden", "w2_oracle.json")
+    gold = json.load(open(path))["rows"]
+    nets = [inputs.ising_2d(64, 64, b) for b in inputs.w2_betas()]
+    hs = [T.create_network(n) for n in nets]
+    for chi, env in ((32, 1), (32, 2)):
+        rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], chi, env)
+        for net, b, r in zip(nets, inputs.w2_betas(), rs):
+            g = next(x for x in gold if x["chi"] == chi and x["env"] == env and abs(x["beta"] - b) < 1e-12)
+            d = abs(r.log_abs - g["log_abs"]) / 4096
+            print(f"W2 beta={b:.6f} chi={chi} env={env}: gpu {r.log_abs!r} oracle {g['log_abs']!r} diff/N {d:.3e}",
+                  flush=True)
+            assert r.sign == g["sign"] and d <= TOL
