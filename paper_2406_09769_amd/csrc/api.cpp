@@ -151,6 +151,7 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
     nd[i].ws = nets[i]->d_ws;
     nd[i].cst = nets[i]->d_const;
     nd[i].sc = nets[i]->d_sc;
+    nd[i].dyn = reinterpret_cast<int32_t *>(nets[i]->d_ws + plans[i]->plan.dyn_off);
   }
   tn::NetDev *d_nd = nullptr;
   if (hipMalloc(&d_nd, n * sizeof(tn::NetDev)) != hipSuccess) return fail(TN_ENOMEM, "launch descriptor allocation failed");
@@ -276,8 +277,8 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int
       r.sign = int32_t(sc[i].sign);
     }
     r.seconds = secs;
-    r.flops = plans[i]->plan.flops;
-    r.eig_flops = plans[i]->plan.eig_flops;
+    r.flops = sc[i].flops;
+    r.eig_flops = sc[i].eig_flops;
     r.n_eig = plans[i]->plan.n_eig;
     r.n_fallback = sc[i].n_fallback;
     r.max_residual = sc[i].max_resid;
@@ -363,7 +364,7 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
   };
   if (hipMalloc(&d_ops, ops.size() * sizeof(tn::Op)) != hipSuccess ||
       hipMalloc(&d_tab, std::max<size_t>(tab.size(), 1) * 4) != hipSuccess ||
-      hipMalloc(&d_ws, std::max<size_t>(ws.size(), 1) * 8) != hipSuccess ||
+      hipMalloc(&d_ws, (ws.size() + 32) * 8) != hipSuccess ||
       hipMalloc(&d_cst, std::max<size_t>(cst.size(), 1) * 8) != hipSuccess ||
       hipMalloc(&d_sc, sizeof(tn::NetScalars)) != hipSuccess ||
       hipMalloc(&d_nd, sizeof(tn::NetDev)) != hipSuccess) {
@@ -372,16 +373,19 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
   }
   tn::NetScalars init{};
   init.sign = 1;
-  tn::NetDev nd{d_ops, int64_t(ops.size()), d_tab, d_ws, d_cst, d_sc};
+  // the first 32 doubles of the diagnostic workspace hold the kept-rank slots
+  tn::NetDev nd{d_ops, int64_t(ops.size()), d_tab, d_ws + 32, d_cst, d_sc, reinterpret_cast<int32_t *>(d_ws)};
   hipError_t e = hipMemcpy(d_ops, ops.data(), ops.size() * sizeof(tn::Op), hipMemcpyHostToDevice);
   if (e == hipSuccess && !tab.empty()) e = hipMemcpy(d_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && !ws.empty()) e = hipMemcpy(d_ws, ws.data(), ws.size() * 8, hipMemcpyHostToDevice);
+  std::vector<int32_t> slots(64, 1);
+  if (e == hipSuccess) e = hipMemcpy(d_ws, slots.data(), 64 * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !ws.empty()) e = hipMemcpy(d_ws + 32, ws.data(), ws.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess && !cst.empty()) e = hipMemcpy(d_cst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_sc, &init, sizeof(init), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_nd, &nd, sizeof(nd), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = tn::launch_interp(d_nd, 1, kp, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e == hipSuccess && !ws.empty()) e = hipMemcpy(ws.data(), d_ws, ws.size() * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && !ws.empty()) e = hipMemcpy(ws.data(), d_ws + 32, ws.size() * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess && sc_out) e = hipMemcpy(sc_out, d_sc, sizeof(tn::NetScalars), hipMemcpyDeviceToHost);
   cleanup();
   if (e != hipSuccess) return fail(TN_EDEVICE, std::string("diagnostic run: ") + hipGetErrorString(e));
@@ -411,6 +415,9 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
   push_map(M, sam, op.am);
   push_map(N, sbn, op.bn);
   op.K = K;
+  op.bm = tn::Box{0, M, {0}, {0}};
+  op.bnb = tn::Box{0, N, {0}, {0}};
+  op.bk_ = tn::Box{0, K, {0}, {0}};
   op.ak = int32_t(tab.size());
   for (int32_t k = 0; k < K; ++k) tab.push_back(int32_t(k * sak));
   op.bk = int32_t(tab.size());
@@ -438,6 +445,8 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *op
   op.kind = tn::OP_EIG;
   op.count = n;
   op.K = ucols;
+  op.bm = tn::Box{0, n, {0}, {0}};
+  op.out_dyn = 0;
   op.a = 0;
   int64_t lsz = (int64_t(n) * n + 31) / 32 * 32;
   op.c = lsz;
@@ -450,7 +459,8 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *op
   tn::NetScalars sc{};
   int rc = run_single({op}, {}, ws, {}, kp, &sc);
   if (rc != TN_OK) return rc;
-  std::memcpy(U, ws.data() + lsz, size_t(n) * ucols * 8);
+  for (int32_t i = 0; i < n; ++i)          // device layout U[j][i] -> host n x ucols
+    for (int32_t j = 0; j < ucols; ++j) U[int64_t(i) * ucols + j] = ws[lsz + int64_t(j) * n + i];
   if (n_fallback) *n_fallback = sc.n_fallback;
   return TN_OK;
 }
@@ -462,7 +472,9 @@ int tn_debug_rescale(double *x, int64_t count, int64_t *exponent) {
   op.kind = tn::OP_RESCALE;
   op.flags = tn::F_ACCUM;
   op.c = 0;
-  op.count = count;
+  op.count = 1;
+  op.bm = tn::Box{0, int32_t(count), {0}, {0}};
+  op.bnb = tn::Box{0, 1, {0}, {0}};
   std::vector<double> ws(x, x + count);
   tn::KeepParams kp{1e-15, 1e-12, tn::kClusterFloor};
   tn::NetScalars sc{};

@@ -6,7 +6,9 @@
 //               every mode permutation into the tile loads.
 //   OP_EIG      symmetric eigensolve of a density matrix (cyclic two-sided Jacobi,
 //               round-robin parallel ordering, matrix resident in LDS) followed by the
-//               keep rule; writes the kept leading eigenvectors, zero-padded.
+//               keep rule; writes the kept leading eigenvectors and the kept rank.
+// MPS bonds have a runtime extent (the kept rank of the eigensolve that made them):
+// tensors keep their static layout and every op touches only the valid box.
 //   OP_RESCALE  exact power-of-two normalisation with the exponent summed in int64.
 //   OP_SCALAR   ln|z| and sign of a closing scalar.
 //   OP_IDENT    identity matrices of the identity insertion.
@@ -30,12 +32,39 @@ __device__ __forceinline__ int64_t map_off(const int32_t *tab, const IdxMap &m, 
   return int64_t(tab[m.hi + h]) + int64_t(tab[m.lo + l]);
 }
 
+// ---------------------------------------------------------------- runtime extents
+
+__device__ __forceinline__ int32_t box_eff(const Box &b, const int32_t *dyn) {
+  int32_t n = b.rest;
+  for (int d = 0; d < b.nd; ++d) n *= dyn[b.id[d]];
+  return n;
+}
+
+// compact index in [0, box_eff) -> static index in the (cap..., rest) layout
+__device__ __forceinline__ int32_t box_conv(const Box &b, const int32_t *dyn, int32_t i) {
+  if (b.nd == 0) return i;
+  int32_t r = i % b.rest;
+  int32_t q = i / b.rest;
+  int32_t s = 0, mult = b.rest;
+  for (int d = b.nd - 1; d >= 0; --d) {
+    const int32_t k = dyn[b.id[d]];
+    s += (q % k) * mult;
+    q /= k;
+    mult *= b.cap[d];
+  }
+  return s + r;
+}
+
 // ---------------------------------------------------------------- GEMM
 
 __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
-                           double *__restrict__ C, const int32_t *__restrict__ tab, double *lds,
-                           int t_begin, int t_step) {
-  const int M = op.am.n, N = op.bn.n, K = op.K;
+                           double *__restrict__ C, const int32_t *__restrict__ tab, const int32_t *dyn,
+                           double *lds, int t_begin, int t_step, NetScalars *sc) {
+  // runtime extents; the output keeps its static row length
+  const int M = box_eff(op.bm, dyn), N = box_eff(op.bnb, dyn), K = box_eff(op.bk_, dyn);
+  const int NS = op.bn.n;
+  const bool kdyn = op.bk_.nd > 0;
+  if (t_begin == 0 && threadIdx.x == 0) sc->flops += 2LL * M * N * K;
   const int tilesN = (N + kTile - 1) / kTile;
   const int ntiles = ((M + kTile - 1) / kTile) * tilesN;
   double *As = lds;                  // [kTK][kPitch], element (k, m)
@@ -59,12 +88,12 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
       ak_[q] = akf ? e % kTK : e / kTile;
       const int m = m0 + ai[q];
       av[q] = m < M;
-      aoff[q] = av[q] ? map_off(tab, op.am, m) : 0;
+      aoff[q] = av[q] ? map_off(tab, op.am, box_conv(op.bm, dyn, m)) : 0;
       bi[q] = bnf ? e % kTile : e / kTK;
       bk_[q] = bnf ? e / kTile : e % kTK;
       const int n = n0 + bi[q];
       bv[q] = n < N;
-      boff[q] = bv[q] ? map_off(tab, op.bn, n) : 0;
+      boff[q] = bv[q] ? map_off(tab, op.bn, box_conv(op.bnb, dyn, n)) : 0;
     }
     v4d acc[2][2];
 #pragma unroll
@@ -77,9 +106,11 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = k0 + ak_[q];
-        va[q] = (av[q] && k < K) ? A[aoff[q] + ak[k]] : 0.0;
+        const int ks = (kdyn && k < K) ? box_conv(op.bk_, dyn, k) : k;
+        va[q] = (av[q] && k < K) ? A[aoff[q] + ak[ks]] : 0.0;
         const int kb = k0 + bk_[q];
-        vb[q] = (bv[q] && kb < K) ? B[boff[q] + bk[kb]] : 0.0;
+        const int kbs = (kdyn && kb < K) ? box_conv(op.bk_, dyn, kb) : kb;
+        vb[q] = (bv[q] && kb < K) ? B[boff[q] + bk[kbs]] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -109,7 +140,8 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
         for (int r = 0; r < 4; ++r) {
           const int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;   // D: lane l, reg r = row l/16 + 4r
           const int col = n0 + wn * 32 + j * 16 + (lane & 15);
-          if (row < M && col < N) C[int64_t(row) * N + col] = acc[i][j][r];
+          if (row < M && col < N)
+            C[int64_t(box_conv(op.bm, dyn, row)) * NS + box_conv(op.bnb, dyn, col)] = acc[i][j][r];
         }
   }
 }
@@ -145,9 +177,17 @@ __device__ double block_sum(double v, double *red) {
 
 // ---------------------------------------------------------------- rescale / scalar
 
-__device__ void rescale_wg(double *x, int64_t count, bool accum, NetScalars *sc, double *red) {
+// x is stored [rows][ncols]; only the runtime box rows x cols is valid.
+__device__ void rescale_wg(const Op &op, double *x, const int32_t *dyn, NetScalars *sc, double *red) {
+  const bool accum = (op.flags & F_ACCUM) != 0;
+  const int32_t R = box_eff(op.bm, dyn), Cn = box_eff(op.bnb, dyn);
+  const int64_t ncols = op.count;
+  const int64_t total = int64_t(R) * Cn;
   double m = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += kThreads) m = fmax(m, fabs(x[i]));
+  for (int64_t i = threadIdx.x; i < total; i += kThreads) {
+    const int32_t r = int32_t(i / Cn), c = int32_t(i - int64_t(r) * Cn);
+    m = fmax(m, fabs(x[int64_t(box_conv(op.bm, dyn, r)) * ncols + box_conv(op.bnb, dyn, c)]));
+  }
   m = block_max(m, red);
   if (!(m > 0.0) || !isfinite(m)) {
     if (m == 0.0 && accum && threadIdx.x == 0) sc->zero = 1;
@@ -155,7 +195,11 @@ __device__ void rescale_wg(double *x, int64_t count, bool accum, NetScalars *sc,
   }
   int e;
   frexp(m, &e);
-  for (int64_t i = threadIdx.x; i < count; i += kThreads) x[i] = ldexp(x[i], -e);
+  for (int64_t i = threadIdx.x; i < total; i += kThreads) {
+    const int32_t r = int32_t(i / Cn), c = int32_t(i - int64_t(r) * Cn);
+    const int64_t o = int64_t(box_conv(op.bm, dyn, r)) * ncols + box_conv(op.bnb, dyn, c);
+    x[o] = ldexp(x[o], -e);
+  }
   if (accum && threadIdx.x == 0) sc->exp_sum += e;
 }
 
@@ -187,12 +231,14 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, d
   s = t * c;
 }
 
-__device__ void eig_keep(const Op &op, double *ws, const KeepParams &kp, NetScalars *sc, double *lds) {
-  const int n = int(op.count);
+__device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
+                         double *lds) {
+  const int ld = int(op.count);            // static dimension = row stride of L and of U
+  const int n = box_eff(op.bm, dyn);       // runtime dimension: the valid leading block
   const int ucols = op.K;
   const int np = n + (n & 1);
   const int half = np / 2;
-  const bool vglob = (op.flags & F_V_GLOBAL) != 0;
+  const bool vglob = (op.flags & F_V_GLOBAL) != 0 && (2 * np * np + 4 * np + 16) > kLdsDoubles;
   double *A = lds;                                   // np x np
   double *V = vglob ? ws + op.b : lds + np * np;     // np x np
   double *aux = lds + np * np + (vglob ? 0 : np * np);
@@ -210,7 +256,7 @@ __device__ void eig_keep(const Op &op, double *ws, const KeepParams &kp, NetScal
   for (int e = tid; e < np * np; e += kThreads) {
     const int i = e / np, j = e % np;
     double v = 0.0;
-    if (i < n && j < n) v = 0.5 * (L[int64_t(i) * n + j] + L[int64_t(j) * n + i]);
+    if (i < n && j < n) v = 0.5 * (L[int64_t(i) * ld + j] + L[int64_t(j) * ld + i]);
     A[e] = v;
     V[e] = (i == j) ? 1.0 : 0.0;
     fro += v * v;
@@ -292,13 +338,15 @@ __device__ void eig_keep(const Op &op, double *ws, const KeepParams &kp, NetScal
       sc->n_fallback += 1;
     }
     flag[1] = k;
+    dyn[op.out_dyn] = k;
+    sc->eig_flops += 9LL * n * n * n;
   }
   __syncthreads();
   const int k = flag[1];
-  double *U = ws + op.c;
-  for (int e = tid; e < n * ucols; e += kThreads) {
-    const int i = e / ucols, j = e % ucols;
-    U[e] = (j < k) ? V[i * np + isrt[j]] : 0.0;
+  double *U = ws + op.c;                  // U[j][i], j < k kept vectors, i < n components
+  for (int e = tid; e < n * k; e += kThreads) {
+    const int j = e / n, i = e % n;
+    U[int64_t(j) * ld + i] = V[i * np + isrt[j]];
   }
 }
 
@@ -313,14 +361,14 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
       case OP_GEMM: {
         const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
         const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-        gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1);
+        gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, nd.dyn, lds, 0, 1, nd.sc);
         break;
       }
       case OP_EIG:
-        eig_keep(op, nd.ws, kp, nd.sc, lds);
+        eig_keep(op, nd.ws, nd.dyn, kp, nd.sc, lds);
         break;
       case OP_RESCALE:
-        rescale_wg(nd.ws + op.c, op.count, (op.flags & F_ACCUM) != 0, nd.sc, lds);
+        rescale_wg(op, nd.ws + op.c, nd.dyn, nd.sc, lds);
         break;
       case OP_SCALAR:
         scalar_wg(nd.ws + op.a, nd.sc);

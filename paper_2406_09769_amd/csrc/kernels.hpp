@@ -14,6 +14,7 @@ struct NetDev {
   double *ws;
   const double *cst;
   NetScalars *sc;
+  int32_t *dyn;      // kept-rank slots (inside the workspace)
 };
 
 // Rank rule of the eigensolve: drop w <= tau_rel*w1; never split a cluster with

@@ -83,6 +83,9 @@ struct Sym {                  // a tensor known by its labelled modes
   std::vector<int64_t> lab, dim;
   int32_t buf = -1;           // virtual workspace buffer; -1 = constant area
   int64_t cst = 0;            // constant-area offset when buf < 0
+  // storage as a [rows][cols] matrix with runtime extents (set for GEMM outputs)
+  Box rows{0, 1, {0}, {0}}, cols{0, 1, {0}, {0}};
+  int64_t ncols = 1;
   int64_t size() const {
     int64_t s = 1;
     for (int64_t d : dim) s *= d;
@@ -117,6 +120,56 @@ class Builder {
   }
 
   int64_t fresh() { return next_label_++; }
+
+  // MPS bonds have a runtime extent (the kept rank) held in a per-network slot.
+  int32_t new_dyn(int64_t label) {
+    int32_t d = n_dyn_++;
+    dynl_[label] = d;
+    return d;
+  }
+  void share_dyn(int64_t label, int64_t copy) {
+    auto it = dynl_.find(label);
+    if (it != dynl_.end()) dynl_[copy] = it->second;
+  }
+  int32_t dyn_of(int64_t label) const {
+    auto it = dynl_.find(label);
+    return it == dynl_.end() ? -1 : it->second;
+  }
+  int32_t n_dyn() const { return n_dyn_; }
+  std::string err;
+
+  struct Group {
+    std::vector<int64_t> lab, dim, sa, sb;   // labels, static dims, strides in A (and B)
+    std::vector<int32_t> dyn;
+  };
+  // bond modes first (stable), so the valid region of the group is a Box
+  static void dyn_first(Group &g) {
+    std::vector<size_t> idx(g.lab.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return (g.dyn[x] >= 0) > (g.dyn[y] >= 0); });
+    Group o;
+    for (size_t i : idx) {
+      o.lab.push_back(g.lab[i]); o.dim.push_back(g.dim[i]); o.dyn.push_back(g.dyn[i]);
+      if (!g.sa.empty()) o.sa.push_back(g.sa[i]);
+      if (!g.sb.empty()) o.sb.push_back(g.sb[i]);
+    }
+    g = o;
+  }
+  Box box_of(const Group &g) {
+    Box b{};
+    int64_t rest = 1;
+    for (size_t i = 0; i < g.lab.size(); ++i) {
+      if (g.dyn[i] >= 0) {
+        if (b.nd >= kMaxDyn) { err = "more than 8 bond modes in one index group"; continue; }
+        b.id[b.nd] = g.dyn[i];
+        b.cap[b.nd] = int32_t(g.dim[i]);
+        b.nd++;
+      } else rest *= g.dim[i];
+    }
+    b.rest = int32_t(rest);
+    p_.max_dyn_modes = std::max<int32_t>(p_.max_dyn_modes, b.nd);
+    return b;
+  }
 
   int32_t new_buf(int64_t size) {
     vb_.push_back({size, -1, -1});
@@ -193,32 +246,48 @@ class Builder {
     return int32_t(p_.ops.size() - 1);
   }
 
-  // Pairwise contraction over all shared labels; A's free modes come first.
+  // Pairwise contraction over all shared labels; A's free modes come first. Within
+  // each index group (A-free, shared, B-free) bond modes are placed first.
   Sym contract_ab(const Sym &A, const Sym &B) {
-    std::vector<int64_t> fa, fad, fas, sk, skd, ska, skb, fb, fbd, fbs;
+    Group ga, gk, gb;
     auto sa = strides_of(A), sb = strides_of(B);
     for (size_t i = 0; i < A.lab.size(); ++i) {
       int j = B.find(A.lab[i]);
-      if (j >= 0) { sk.push_back(A.lab[i]); skd.push_back(A.dim[i]); ska.push_back(sa[i]); skb.push_back(sb[j]); }
-      else { fa.push_back(A.lab[i]); fad.push_back(A.dim[i]); fas.push_back(sa[i]); }
+      if (j >= 0) {
+        gk.lab.push_back(A.lab[i]); gk.dim.push_back(A.dim[i]); gk.sa.push_back(sa[i]); gk.sb.push_back(sb[j]);
+        gk.dyn.push_back(dyn_of(A.lab[i]));
+      } else {
+        ga.lab.push_back(A.lab[i]); ga.dim.push_back(A.dim[i]); ga.sa.push_back(sa[i]); ga.dyn.push_back(dyn_of(A.lab[i]));
+      }
     }
     for (size_t i = 0; i < B.lab.size(); ++i)
-      if (A.find(B.lab[i]) < 0) { fb.push_back(B.lab[i]); fbd.push_back(B.dim[i]); fbs.push_back(sb[i]); }
+      if (A.find(B.lab[i]) < 0) {
+        gb.lab.push_back(B.lab[i]); gb.dim.push_back(B.dim[i]); gb.sa.push_back(sb[i]); gb.dyn.push_back(dyn_of(B.lab[i]));
+      }
+    dyn_first(ga);
+    dyn_first(gk);
+    dyn_first(gb);
     Sym out;
-    out.lab = fa; out.lab.insert(out.lab.end(), fb.begin(), fb.end());
-    out.dim = fad; out.dim.insert(out.dim.end(), fbd.begin(), fbd.end());
+    out.lab = ga.lab; out.lab.insert(out.lab.end(), gb.lab.begin(), gb.lab.end());
+    out.dim = ga.dim; out.dim.insert(out.dim.end(), gb.dim.begin(), gb.dim.end());
     out.buf = new_buf(out.size());
     Op o{};
     o.kind = OP_GEMM;
-    o.am = make_map(fad, fas);
-    o.bn = make_map(fbd, fbs);
+    o.am = make_map(ga.dim, ga.sa);
+    o.bn = make_map(gb.dim, gb.sa);
     int64_t K = 1;
-    for (int64_t d : skd) K *= d;
+    for (int64_t d : gk.dim) K *= d;
     o.K = int32_t(K);
-    o.ak = table(skd, ska);
-    o.bk = table(skd, skb);
-    if (!ska.empty() && ska.back() == 1) o.flags |= F_A_KFAST;
-    if (fbs.empty() || fbs.back() == 1) o.flags |= F_B_NFAST;
+    o.ak = table(gk.dim, gk.sa);
+    o.bk = table(gk.dim, gk.sb);
+    o.bm = box_of(ga);
+    o.bnb = box_of(gb);
+    o.bk_ = box_of(gk);
+    if (!gk.sa.empty() && gk.sa.back() == 1) o.flags |= F_A_KFAST;
+    if (gb.sa.empty() || gb.sa.back() == 1) o.flags |= F_B_NFAST;
+    out.rows = o.bm;
+    out.cols = o.bnb;
+    out.ncols = o.bn.n;
     int32_t id = emit(o);
     bind(id, 1, A);
     bind(id, 2, B);
@@ -278,7 +347,9 @@ class Builder {
   void rescale(const Sym &s, bool accum) {
     Op o{};
     o.kind = OP_RESCALE;
-    o.count = s.size();
+    o.count = s.ncols;
+    o.bm = s.rows;
+    o.bnb = s.cols;
     if (accum) o.flags |= F_ACCUM;
     int32_t id = emit(o);
     refs_.push_back({id, 0, s.buf});
@@ -290,6 +361,7 @@ class Builder {
     s.lab = {l0, l1};
     s.dim = {d, d};
     s.buf = new_buf(d * d);
+    s.rows.rest = int32_t(d * d);
     Op o{};
     o.kind = OP_IDENT;
     o.count = d;
@@ -298,16 +370,26 @@ class Builder {
     return s;
   }
 
-  Sym eig(const Sym &L, int64_t n, int64_t ucols, const std::vector<int64_t> &row_lab,
-          const std::vector<int64_t> &row_dim, int64_t bond) {
+  // Kept leading eigenvectors of L (rows = its first nrow modes, bond modes first).
+  // U is stored [bond][rows] so that the new bond is the outermost mode.
+  Sym eig(const Sym &L, size_t nrow, int64_t ucols, int64_t bond) {
+    int64_t n = 1;
+    for (size_t i = 0; i < nrow; ++i) n *= L.dim[i];
     Sym U;
-    U.lab = row_lab; U.lab.push_back(bond);
-    U.dim = row_dim; U.dim.push_back(ucols);
+    U.lab.push_back(bond);
+    U.dim.push_back(ucols);
+    for (size_t i = 0; i < nrow; ++i) { U.lab.push_back(L.lab[i]); U.dim.push_back(L.dim[i]); }
     U.buf = new_buf(n * ucols);
+    int32_t slot = new_dyn(bond);
     Op o{};
     o.kind = OP_EIG;
     o.count = n;
     o.K = int32_t(ucols);
+    o.bm = L.rows;
+    o.out_dyn = slot;
+    U.rows = Box{1, 1, {slot}, {int32_t(ucols)}};
+    U.cols = L.rows;
+    U.ncols = n;
     const int64_t np = n + (n & 1);
     bool vglobal = (2 * np * np + 4 * np + 16) > kLdsDoubles;
     int32_t scratch = -1;
@@ -336,7 +418,10 @@ class Builder {
     using Act = std::pair<int32_t, int32_t>;  // (last use, buffer)
     std::priority_queue<Act, std::vector<Act>, std::greater<Act>> active;
     std::vector<int64_t> off(vb_.size(), 0);
-    int64_t top = 0;
+    const int64_t dyn_doubles = ((int64_t(n_dyn_) + 1) / 2 + kAlign - 1) / kAlign * kAlign;
+    p_.dyn_off = 0;
+    p_.n_dyn = n_dyn_;
+    int64_t top = dyn_doubles;
     auto release = [&](int32_t b) {
       int64_t o = off[b], s = (vb_[b].size + kAlign - 1) / kAlign * kAlign;
       auto it = freel.emplace(o, s).first;
@@ -391,6 +476,8 @@ class Builder {
   std::vector<VB> vb_;
   std::vector<Ref> refs_;
   std::map<std::vector<int32_t>, int32_t> cache_;
+  std::unordered_map<int64_t, int32_t> dynl_;
+  int32_t n_dyn_ = 0;
 };
 
 struct Key {            // sort key of a new leaf
@@ -649,6 +736,7 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
       if (it != bra.end()) return it->second;
       int64_t b = B.fresh();
       bra[l] = b;
+      B.share_dyn(l, b);
       return b;
     };
     auto check_labels = [&](const Sym &s, std::vector<int64_t> want) -> bool {
@@ -691,12 +779,9 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
     std::vector<int64_t> rows = {leaf[0], leaf[1]};
     std::vector<MpsTensor> next;
     for (int64_t k = 2; k <= n - 1; ++k) {
-      // row modes of C in C's own order
-      std::vector<int64_t> rl, rd;
-      for (size_t i = 0; i < C.lab.size(); ++i)
-        if (std::find(rows.begin(), rows.end(), C.lab[i]) != rows.end()) { rl.push_back(C.lab[i]); rd.push_back(C.dim[i]); }
       int64_t nr = 1;
-      for (int64_t d : rd) nr *= d;
+      for (size_t i = 0; i < C.lab.size(); ++i)
+        if (std::find(rows.begin(), rows.end(), C.lab[i]) != rows.end()) nr *= C.dim[i];
       if (nr > kMaxEigDim) {
         *unsupported = true;
         return "density matrix of dimension " + std::to_string(nr) + " exceeds the supported 128";
@@ -707,7 +792,7 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
       Sym L = B.contract_ab(T, Cb);              // rows x bra(rows)
       int64_t ucols = std::min<int64_t>({int64_t(a.chi), nr, xdim(k)});
       int64_t bond = B.fresh();
-      Sym U = B.eig(L, nr, ucols, rl, rd, bond);
+      Sym U = B.eig(L, rows.size(), ucols, bond);
       Sym Cn = B.contract_ab(U, C);              // bond x X_k
       Cn = B.absorb(&Cn, gsyms(k + 1));
       std::vector<int64_t> want = k + 1 <= n - 1 ? X[k + 1] : std::vector<int64_t>();
@@ -724,8 +809,9 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
     leaves = leaf;
     for (int32_t v : part) absorbed[v] = 1;
   }
-  js << "]}";
+  js << "],\"max_dyn_modes\":" << out.max_dyn_modes << ",\"n_eig\":" << out.n_eig << "}";
   out.plan_json = js.str();
+  if (!B.err.empty()) { *unsupported = true; return B.err; }
   B.allocate();
   return "";
 }

@@ -33,6 +33,9 @@ struct Plan {
   int64_t eig_flops = 0;     // 9 n^3 per density matrix
   int64_t n_eig = 0;
   int32_t max_eig_dim = 0;
+  int64_t dyn_off = 0;       // workspace offset (doubles) of the int32 kept-rank slots
+  int32_t n_dyn = 0;
+  int32_t max_dyn_modes = 0; // most bond modes met in one GEMM index group
   std::string plan_json;     // structural plan (leaf orders and placements)
 };
 

@@ -32,22 +32,35 @@ struct IdxMap {
   int64_t hi;     // table offset of the outer part
   int64_t lo;     // table offset of the inner part
   int32_t lo_n;   // size of the inner part
-  int32_t n;      // total extent
+  int32_t n;      // total (static) extent
+};
+
+// Runtime extent of a flattened index group whose leading modes are MPS bonds.
+// Static layout: (cap[0], ..., cap[nd-1], rest) row-major. At run time only
+// bond indices below the kept rank dyn[id[d]] are valid, so the valid entries
+// are the compact range [0, prod(dyn) * rest) mapped back by mixed radix.
+constexpr int kMaxDyn = 8;
+struct Box {
+  int32_t nd;
+  int32_t rest;
+  int32_t id[kMaxDyn];
+  int32_t cap[kMaxDyn];
 };
 
 struct Op {
   int32_t kind;
   int32_t flags;
-  int64_t c;        // GEMM/EIG/IDENT output offset; RESCALE/SCALAR operand offset
-  int64_t a;        // GEMM A; EIG input L
+  int64_t c;        // GEMM/EIG/IDENT output offset; RESCALE operand offset
+  int64_t a;        // GEMM A; EIG input L; SCALAR operand
   int64_t b;        // GEMM B; EIG scratch (V) when F_V_GLOBAL
-  int64_t count;    // RESCALE element count; EIG: matrix dim n; IDENT: dim
-  int32_t K;        // GEMM contraction extent; EIG: ucols (static kept columns)
+  int64_t count;    // IDENT: dim; EIG: static dim of L; RESCALE: static row length
+  int32_t K;        // GEMM static contraction extent; EIG: ucols (static kept columns)
   int32_t ak;       // GEMM: table offset of A's k offsets
   int32_t bk;       // GEMM: table offset of B's k offsets
-  int32_t pad;
-  IdxMap am;        // GEMM: A row map (extent M)
-  IdxMap bn;        // GEMM: B column map (extent N)
+  int32_t out_dyn;  // EIG: dyn slot that receives the kept rank
+  IdxMap am;        // GEMM: A row map (static extent M)
+  IdxMap bn;        // GEMM: B column map (static extent N)
+  Box bm, bnb, bk_; // runtime extents of the M, N and K groups (RESCALE: rows, cols)
 };
 
 // Scalars each network accumulates on the device.
@@ -59,7 +72,8 @@ struct NetScalars {
   long long zero;     // 1 once Z is exactly zero
   long long n_fallback;
   long long n_learned;
-  long long pad;
+  long long flops;      // executed GEMM flops, 2 m n k at the runtime extents
+  long long eig_flops;  // 9 n^3 per density matrix at its runtime dimension
 };
 
 }  // namespace tn
