@@ -119,6 +119,10 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     value = len(nets) / (ms_per_step / 1e3)
 
+    prof = {}
+    for name, i in (("beta0.44_chi64_env1", 8 * 2 + 3), ("beta0.44_chi32_env1", 3)):
+        prof[name] = {k: round(v, 4) for k, v in T.tn_profile_last(handles[i]).items()}
+    print(f"[bench] per-op device seconds of one network: {json.dumps(prof)}", file=sys.stderr, flush=True)
     flops = sum(r.flops for r in rs)
     eig_flops = sum(r.eig_flops for r in rs)
     ksec = sum(kernel_s) / len(kernel_s)

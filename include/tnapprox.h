@@ -157,6 +157,11 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
 int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *opt, double *U,
                  int64_t *n_fallback);
 
+/* Device time of the last contraction of net, split by op kind: seconds_by_kind[k]
+ * for k = 1 GEMM, 2 eigensolve, 3 rescale, 4 closing scalar, 5 identity (8 entries;
+ * measured by the first thread of the network's workgroup with the wall clock). */
+int tn_profile_last(tn_net net, double *seconds_by_kind);
+
 /* x <- x * 2^-e with e the frexp exponent of max|x|; returns e. */
 int tn_debug_rescale(double *x, int64_t count, int64_t *exponent);
 

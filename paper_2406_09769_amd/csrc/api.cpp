@@ -71,6 +71,7 @@ int read_path(const tn_path *path, int32_t nt, std::vector<std::vector<int32_t>>
 
 struct tn_net_s {
   tn::Graph g;
+  tn::NetScalars last{};     // device scalars of the last contraction
   double *d_const = nullptr;
   double *d_ws = nullptr;
   int64_t ws_cap = 0;
@@ -267,6 +268,7 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int
   int rc = run_batch(v, plans, o, &secs, sc);
   if (rc != TN_OK) return rc;
   for (int32_t i = 0; i < n; ++i) {
+    v[i]->last = sc[i];
     tn_result &r = outs[i];
     std::memset(&r, 0, sizeof(r));
     if (sc[i].zero) {
@@ -345,6 +347,16 @@ int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env
   stats[4] = dp->plan.eig_flops;
   stats[5] = dp->plan.n_eig;
   stats[6] = dp->plan.max_eig_dim;
+  return TN_OK;
+}
+
+int tn_profile_last(tn_net net, double *seconds_by_kind) {
+  g_err.clear();
+  if (!net || !seconds_by_kind) return fail(TN_EINVAL, "null arguments");
+  int dev = 0, khz = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  for (int k = 0; k < 8; ++k) seconds_by_kind[k] = khz > 0 ? double(net->last.ticks[k]) / (double(khz) * 1e3) : 0.0;
   return TN_OK;
 }
 

@@ -34,20 +34,22 @@ __device__ __forceinline__ int64_t map_off(const int32_t *tab, const IdxMap &m, 
 
 // ---------------------------------------------------------------- runtime extents
 
-__device__ __forceinline__ int32_t box_eff(const Box &b, const int32_t *dyn) {
+// The interpreter stages each op in LDS and replaces every Box's slot ids by the
+// runtime extents they hold, so these helpers read extents straight from b.id.
+__device__ __forceinline__ int32_t box_eff(const Box &b) {
   int32_t n = b.rest;
-  for (int d = 0; d < b.nd; ++d) n *= dyn[b.id[d]];
+  for (int d = 0; d < b.nd; ++d) n *= b.id[d];
   return n;
 }
 
 // compact index in [0, box_eff) -> static index in the (cap..., rest) layout
-__device__ __forceinline__ int32_t box_conv(const Box &b, const int32_t *dyn, int32_t i) {
+__device__ __forceinline__ int32_t box_conv(const Box &b, int32_t i) {
   if (b.nd == 0) return i;
   int32_t r = i % b.rest;
   int32_t q = i / b.rest;
   int32_t s = 0, mult = b.rest;
   for (int d = b.nd - 1; d >= 0; --d) {
-    const int32_t k = dyn[b.id[d]];
+    const int32_t k = b.id[d];
     s += (q % k) * mult;
     q /= k;
     mult *= b.cap[d];
@@ -57,24 +59,34 @@ __device__ __forceinline__ int32_t box_conv(const Box &b, const int32_t *dyn, in
 
 // ---------------------------------------------------------------- GEMM
 
+constexpr int kKCache = 4096;          // k offsets cached in LDS when K <= kKCache
+
 __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
-                           double *__restrict__ C, const int32_t *__restrict__ tab, const int32_t *dyn,
-                           double *lds, int t_begin, int t_step, NetScalars *sc) {
+                           double *__restrict__ C, const int32_t *__restrict__ tab, double *lds,
+                           int t_begin, int t_step, NetScalars *sc) {
   // runtime extents; the output keeps its static row length
-  const int M = box_eff(op.bm, dyn), N = box_eff(op.bnb, dyn), K = box_eff(op.bk_, dyn);
+  const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
   const int NS = op.bn.n;
-  const bool kdyn = op.bk_.nd > 0;
   if (t_begin == 0 && threadIdx.x == 0) sc->flops += 2LL * M * N * K;
   const int tilesN = (N + kTile - 1) / kTile;
   const int ntiles = ((M + kTile - 1) / kTile) * tilesN;
   double *As = lds;                  // [kTK][kPitch], element (k, m)
   double *Bs = lds + kTK * kPitch;   // [kTK][kPitch], element (k, n)
+  int32_t *kA = reinterpret_cast<int32_t *>(lds + 2 * kTK * kPitch);   // A's k offsets
+  int32_t *kB = kA + kKCache;                                          // B's k offsets
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const bool akf = (op.flags & F_A_KFAST) != 0;
   const bool bnf = (op.flags & F_B_NFAST) != 0;
-  const int32_t *ak = tab + op.ak;
-  const int32_t *bk = tab + op.bk;
+  const bool kcached = K <= kKCache;
+  if (kcached) {
+    for (int k = tid; k < K; k += kThreads) {
+      const int ks = box_conv(op.bk_, k);
+      kA[k] = tab[op.ak + ks];
+      kB[k] = tab[op.bk + ks];
+    }
+    __syncthreads();
+  }
 
   for (int tile = t_begin; tile < ntiles; tile += t_step) {
     const int m0 = (tile / tilesN) * kTile, n0 = (tile % tilesN) * kTile;
@@ -88,36 +100,42 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
       ak_[q] = akf ? e % kTK : e / kTile;
       const int m = m0 + ai[q];
       av[q] = m < M;
-      aoff[q] = av[q] ? map_off(tab, op.am, box_conv(op.bm, dyn, m)) : 0;
+      aoff[q] = av[q] ? map_off(tab, op.am, box_conv(op.bm, m)) : 0;
       bi[q] = bnf ? e % kTile : e / kTK;
       bk_[q] = bnf ? e / kTile : e % kTK;
       const int n = n0 + bi[q];
       bv[q] = n < N;
-      boff[q] = bv[q] ? map_off(tab, op.bn, box_conv(op.bnb, dyn, n)) : 0;
+      boff[q] = bv[q] ? map_off(tab, op.bn, box_conv(op.bnb, n)) : 0;
     }
+    double va[4], vb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + ak_[q];
+        double x = 0.0;
+        if (av[q] && k < K) x = A[aoff[q] + (kcached ? kA[k] : tab[op.ak + box_conv(op.bk_, k)])];
+        va[q] = x;
+        const int kb = k0 + bk_[q];
+        double y = 0.0;
+        if (bv[q] && kb < K) y = B[boff[q] + (kcached ? kB[kb] : tab[op.bk + box_conv(op.bk_, kb)])];
+        vb[q] = y;
+      }
+    };
     v4d acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
+    load(0);
     for (int k0 = 0; k0 < K; k0 += kTK) {
-      double va[4], vb[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + ak_[q];
-        const int ks = (kdyn && k < K) ? box_conv(op.bk_, dyn, k) : k;
-        va[q] = (av[q] && k < K) ? A[aoff[q] + ak[ks]] : 0.0;
-        const int kb = k0 + bk_[q];
-        const int kbs = (kdyn && kb < K) ? box_conv(op.bk_, dyn, kb) : kb;
-        vb[q] = (bv[q] && kb < K) ? B[boff[q] + bk[kbs]] : 0.0;
-      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         As[ak_[q] * kPitch + ai[q]] = va[q];
         Bs[bk_[q] * kPitch + bi[q]] = vb[q];
       }
       __syncthreads();
+      if (k0 + kTK < K) load(k0 + kTK);   // next slice in flight during the MFMAs
 #pragma unroll
       for (int kk = 0; kk < kTK; kk += 4) {
         const int kr = kk + (lane >> 4);
@@ -141,7 +159,7 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
           const int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;   // D: lane l, reg r = row l/16 + 4r
           const int col = n0 + wn * 32 + j * 16 + (lane & 15);
           if (row < M && col < N)
-            C[int64_t(box_conv(op.bm, dyn, row)) * NS + box_conv(op.bnb, dyn, col)] = acc[i][j][r];
+            C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = acc[i][j][r];
         }
   }
 }
@@ -178,15 +196,15 @@ __device__ double block_sum(double v, double *red) {
 // ---------------------------------------------------------------- rescale / scalar
 
 // x is stored [rows][ncols]; only the runtime box rows x cols is valid.
-__device__ void rescale_wg(const Op &op, double *x, const int32_t *dyn, NetScalars *sc, double *red) {
+__device__ void rescale_wg(const Op &op, double *x, NetScalars *sc, double *red) {
   const bool accum = (op.flags & F_ACCUM) != 0;
-  const int32_t R = box_eff(op.bm, dyn), Cn = box_eff(op.bnb, dyn);
+  const int32_t R = box_eff(op.bm), Cn = box_eff(op.bnb);
   const int64_t ncols = op.count;
   const int64_t total = int64_t(R) * Cn;
   double m = 0.0;
   for (int64_t i = threadIdx.x; i < total; i += kThreads) {
     const int32_t r = int32_t(i / Cn), c = int32_t(i - int64_t(r) * Cn);
-    m = fmax(m, fabs(x[int64_t(box_conv(op.bm, dyn, r)) * ncols + box_conv(op.bnb, dyn, c)]));
+    m = fmax(m, fabs(x[int64_t(box_conv(op.bm, r)) * ncols + box_conv(op.bnb, c)]));
   }
   m = block_max(m, red);
   if (!(m > 0.0) || !isfinite(m)) {
@@ -197,7 +215,7 @@ __device__ void rescale_wg(const Op &op, double *x, const int32_t *dyn, NetScala
   frexp(m, &e);
   for (int64_t i = threadIdx.x; i < total; i += kThreads) {
     const int32_t r = int32_t(i / Cn), c = int32_t(i - int64_t(r) * Cn);
-    const int64_t o = int64_t(box_conv(op.bm, dyn, r)) * ncols + box_conv(op.bnb, dyn, c);
+    const int64_t o = int64_t(box_conv(op.bm, r)) * ncols + box_conv(op.bnb, c);
     x[o] = ldexp(x[o], -e);
   }
   if (accum && threadIdx.x == 0) sc->exp_sum += e;
@@ -234,7 +252,7 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, d
 __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
                          double *lds) {
   const int ld = int(op.count);            // static dimension = row stride of L and of U
-  const int n = box_eff(op.bm, dyn);       // runtime dimension: the valid leading block
+  const int n = box_eff(op.bm);            // runtime dimension: the valid leading block
   const int ucols = op.K;
   const int np = n + (n & 1);
   const int half = np / 2;
@@ -354,21 +372,35 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
 
 __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restrict__ nets, KeepParams kp) {
   __shared__ double lds[kLdsDoubles];
+  __shared__ Op s_op;                 // the current op, Box slot ids replaced by extents
   const NetDev nd = nets[blockIdx.x];
+  const int tid = threadIdx.x;
+  constexpr int kOpWords = int(sizeof(Op) / 4);
+  static_assert(kOpWords <= kThreads, "Op must be staged by one pass of the workgroup");
   for (int64_t i = 0; i < nd.n_ops; ++i) {
-    const Op op = nd.ops[i];
-    switch (op.kind) {
+    if (tid < kOpWords) reinterpret_cast<int32_t *>(&s_op)[tid] = reinterpret_cast<const int32_t *>(nd.ops + i)[tid];
+    __syncthreads();
+    if (tid < 3 * kMaxDyn) {
+      Box *bx = tid < kMaxDyn ? &s_op.bm : (tid < 2 * kMaxDyn ? &s_op.bnb : &s_op.bk_);
+      const int d = tid % kMaxDyn;
+      if (d < bx->nd) bx->id[d] = nd.dyn[bx->id[d]];
+    }
+    __syncthreads();
+    const Op &op = s_op;
+    const int kind = op.kind;
+    const long long t0 = wall_clock64();
+    switch (kind) {
       case OP_GEMM: {
         const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
         const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-        gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, nd.dyn, lds, 0, 1, nd.sc);
+        gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1, nd.sc);
         break;
       }
       case OP_EIG:
         eig_keep(op, nd.ws, nd.dyn, kp, nd.sc, lds);
         break;
       case OP_RESCALE:
-        rescale_wg(op, nd.ws + op.c, nd.dyn, nd.sc, lds);
+        rescale_wg(op, nd.ws + op.c, nd.sc, lds);
         break;
       case OP_SCALAR:
         scalar_wg(nd.ws + op.a, nd.sc);
@@ -380,6 +412,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
         break;
     }
     __syncthreads();
+    if (tid == 0) nd.sc->ticks[kind & 7] += wall_clock64() - t0;
   }
 }
 

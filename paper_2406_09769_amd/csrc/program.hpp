@@ -74,6 +74,7 @@ struct NetScalars {
   long long n_learned;
   long long flops;      // executed GEMM flops, 2 m n k at the runtime extents
   long long eig_flops;  // 9 n^3 per density matrix at its runtime dimension
+  long long ticks[8];   // wall-clock ticks spent per op kind (index = OpKind)
 };
 
 }  // namespace tn

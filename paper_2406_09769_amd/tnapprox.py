@@ -73,6 +73,7 @@ def _load():
         "tn_debug_eig": (C.c_int, [P(C.c_double), C.c_int32, C.c_int32, P(tn_options), P(C.c_double),
                                    P(C.c_int64)]),
         "tn_debug_rescale": (C.c_int, [P(C.c_double), C.c_int64, P(C.c_int64)]),
+        "tn_profile_last": (C.c_int, [C.c_void_p, P(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -220,6 +221,12 @@ def tn_plan_stats(h: Handle, slices, max_rank: int, env_size: int) -> dict:
     _check(LIB.tn_plan_stats(h.ptr, C.byref(p.path), int(max_rank), int(env_size), st))
     keys = ["ops", "table_entries", "ws_doubles", "flops", "eig_flops", "n_eig", "max_eig_dim"]
     return dict(zip(keys, list(st)))
+
+
+def tn_profile_last(h: Handle) -> dict:
+    out = (C.c_double * 8)()
+    _check(LIB.tn_profile_last(h.ptr, out))
+    return {"gemm": out[1], "eig": out[2], "rescale": out[3], "scalar": out[4], "ident": out[5]}
 
 
 def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30) -> np.ndarray:
