@@ -158,7 +158,9 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *op
                  int64_t *n_fallback);
 
 /* Device time of the last contraction of net, split by op kind: seconds_by_kind[k]
- * for k = 1 GEMM, 2 eigensolve, 3 rescale, 4 closing scalar, 5 identity (8 entries;
+ * for k = 1 GEMM, 2 eigensolve, 3 rescale, 4 closing scalar, 5 identity; inside the
+ * eigensolve, 0 = tridiagonal reduction, 6 = QL iteration, 7 = ordering and
+ * back-transformation; entry 8 holds the number of QL rotations (9 entries;
  * measured by the first thread of the network's workgroup with the wall clock). */
 int tn_profile_last(tn_net net, double *seconds_by_kind);
 

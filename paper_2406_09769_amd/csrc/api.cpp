@@ -357,6 +357,7 @@ int tn_profile_last(tn_net net, double *seconds_by_kind) {
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
   for (int k = 0; k < 8; ++k) seconds_by_kind[k] = khz > 0 ? double(net->last.ticks[k]) / (double(khz) * 1e3) : 0.0;
+  seconds_by_kind[8] = double(net->last.n_rot);   // QL rotations of the last contraction
   return TN_OK;
 }
 
@@ -464,8 +465,8 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *op
   op.c = lsz;
   int64_t usz = (int64_t(n) * ucols + 31) / 32 * 32;
   op.b = lsz + usz;
-  if (2 * np * np + 4 * np + 16 > 20000) op.flags |= tn::F_V_GLOBAL;
-  std::vector<double> ws(lsz + usz + np * np, 0.0);
+  op.flags |= tn::F_V_GLOBAL;
+  std::vector<double> ws(lsz + usz + np * np + np, 0.0);
   std::memcpy(ws.data(), L, size_t(n) * n * 8);
   tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
   tn::NetScalars sc{};

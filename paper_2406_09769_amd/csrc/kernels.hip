@@ -4,9 +4,9 @@
 //   OP_GEMM     pairwise contraction as a 64x64-tiled FP64 GEMM on the matrix cores
 //               (v_mfma_f64_16x16x4f64); operand gathers through index tables fold
 //               every mode permutation into the tile loads.
-//   OP_EIG      symmetric eigensolve of a density matrix (cyclic two-sided Jacobi,
-//               round-robin parallel ordering, matrix resident in LDS) followed by the
-//               keep rule; writes the kept leading eigenvectors and the kept rank.
+//   OP_EIG      symmetric eigensolve of a density matrix (Householder tridiagonal
+//               reduction, implicit QL, back-transformation of the kept vectors)
+//               followed by the keep rule; writes the kept eigenvectors and rank.
 // MPS bonds have a runtime extent (the kept rank of the eigensolve that made them):
 // tensors keep their static layout and every op touches only the valid box.
 //   OP_RESCALE  exact power-of-two normalisation with the exponent summed in int64.
@@ -164,6 +164,29 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
   }
 }
 
+// ---------------------------------------------------------------- lane access
+
+// value of v in lane `src` (src wave-uniform), as a wave-uniform scalar
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+// `old` with lane `dst` replaced by the wave-uniform value x (a per-lane select)
+__device__ __forceinline__ double lane_write(double x, int dst, double old) {
+  return (int(threadIdx.x & 63) == dst) ? x : old;
+}
+
+// 1/sqrt(q) for q > 0: hardware estimate refined by two Newton steps (a few ulps;
+// every Givens rotation of the QL sweep needs one, on its critical path)
+__device__ __forceinline__ double rsqrt_nr(double q) {
+  double y = __builtin_amdgcn_rsq(q);
+  const double h = 0.5 * q;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 // ---------------------------------------------------------------- reductions
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -238,108 +261,192 @@ __device__ void ident_wg(double *x, int64_t d) {
 
 // ---------------------------------------------------------------- eigensolver
 
-// Rotation that annihilates a_pq (Golub-Van Loan symmetric Schur step):
-// tau = (a_qq - a_pp) / (2 a_pq), t = sgn(tau) / (|tau| + sqrt(1 + tau^2)).
-__device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, double &c, double &s) {
-  const double tau = (aqq - app) / (2.0 * apq);
-  double t;
-  if (fabs(tau) > 1e150) t = 0.5 / tau;
-  else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  c = 1.0 / sqrt(1.0 + t * t);
-  s = t * c;
-}
-
+// Symmetric eigensolve of the density matrix and the keep rule.
+//  1. Householder reduction to tridiagonal form T = Q^T A Q in LDS (256 threads);
+//     the reflectors go to the op's workspace scratch for the back-transformation.
+//  2. Implicit QL with shifts on T, accumulating the rotations into Z (T = Z W Z^T).
+//     The scalar recurrence is sequential, so every wave runs it on its own copy of
+//     (d, e) without barriers and each thread applies the rotations to its row of Z.
+//  3. Eigenvalues sorted in descending order, the keep rule picks k, and only the k
+//     kept columns of Z are transformed back with the reflectors: U = Q Z_kept.
 __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
                          double *lds) {
   const int ld = int(op.count);            // static dimension = row stride of L and of U
   const int n = box_eff(op.bm);            // runtime dimension: the valid leading block
   const int ucols = op.K;
-  const int np = n + (n & 1);
-  const int half = np / 2;
-  const bool vglob = (op.flags & F_V_GLOBAL) != 0 && (2 * np * np + 4 * np + 16) > kLdsDoubles;
-  double *A = lds;                                   // np x np
-  double *V = vglob ? ws + op.b : lds + np * np;     // np x np
-  double *aux = lds + np * np + (vglob ? 0 : np * np);
-  double *cs = aux;                // [half]
-  double *sn = aux + half;         // [half]
-  double *wsrt = aux + 2 * half;   // [np] sorted eigenvalues
-  int *pq = reinterpret_cast<int *>(aux + 2 * half + np);   // [2*half]
-  int *isrt = pq + 2 * half;                                 // [np]
-  int *flag = isrt + np;                                     // [2]
-  double *red = reinterpret_cast<double *>(flag + 4);        // [4]
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int pa = n + 1;                    // odd LDS pitch of A: conflict-free row access
+  double *A = lds;                         // n x pa during the reduction, then Z (column-major n x n)
+  double *Z = lds;
+  double *vv = lds + n * pa;               // Householder vector of the current step
+  double *pp = vv + n;
+  double *ww = pp + n;
+  double *dd = ww + n;                     // diagonal of T
+  double *ee = dd + n;                     // off-diagonal of T (ee[n-1] = 0)
+  double *dW = ee + n;                     // per-wave copies of (d, e): 4 x 2n
+  double *wsrt = dW + 8 * n;               // eigenvalues, descending
+  int *isrt = reinterpret_cast<int *>(wsrt + n);
+  int *flag = isrt + n + (n & 1);
+  double *red = reinterpret_cast<double *>(flag + 4);
+  double *hv = ws + op.b;                  // reflectors: v_j at hv[j*n + i], beta_j at hv[n*n + j]
   const double *L = ws + op.a;
-  const int tid = threadIdx.x;
 
-  double fro = 0.0;
-  for (int e = tid; e < np * np; e += kThreads) {
-    const int i = e / np, j = e % np;
-    double v = 0.0;
-    if (i < n && j < n) v = 0.5 * (L[int64_t(i) * ld + j] + L[int64_t(j) * ld + i]);
-    A[e] = v;
-    V[e] = (i == j) ? 1.0 : 0.0;
-    fro += v * v;
+  long long tph = wall_clock64();
+  for (int e = tid; e < n * n; e += kThreads) {
+    const int i = e / n, j = e % n;
+    A[i * pa + j] = 0.5 * (L[int64_t(i) * ld + j] + L[int64_t(j) * ld + i]);
   }
-  fro = sqrt(block_sum(fro, red));
-  const double thr = fmax(1e-18 * fro, 1e-300);
   __syncthreads();
 
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) flag[0] = 0;
-    __syncthreads();
-    for (int r = 0; r < np - 1; ++r) {
-      if (tid < half) {
-        int p, q;
-        if (tid == 0) { p = r; q = np - 1; }
-        else { p = (r + tid) % (np - 1); q = (r - tid + np - 1) % (np - 1); }
-        const double apq = A[p * np + q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > thr) {
-          jacobi_rot(A[p * np + p], A[q * np + q], apq, c, s);
-          flag[0] = 1;
-        }
-        pq[2 * tid] = p;
-        pq[2 * tid + 1] = q;
-        cs[tid] = c;
-        sn[tid] = s;
-      }
-      __syncthreads();
-      for (int blk = tid; blk < half * half; blk += kThreads) {
-        const int tp = blk / half, tq = blk % half;
-        const double c1 = cs[tp], s1 = sn[tp], c2 = cs[tq], s2 = sn[tq];
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        const int p = pq[2 * tp], q = pq[2 * tp + 1], rr = pq[2 * tq], ss = pq[2 * tq + 1];
-        const double apr = A[p * np + rr], aps = A[p * np + ss], aqr = A[q * np + rr], aqs = A[q * np + ss];
-        const double xpr = c1 * apr - s1 * aqr, xps = c1 * aps - s1 * aqs;
-        const double xqr = s1 * apr + c1 * aqr, xqs = s1 * aps + c1 * aqs;
-        A[p * np + rr] = c2 * xpr - s2 * xps;
-        A[p * np + ss] = s2 * xpr + c2 * xps;
-        A[q * np + rr] = c2 * xqr - s2 * xqs;
-        A[q * np + ss] = s2 * xqr + c2 * xqs;
-        if (tp == tq) { A[p * np + q] = 0.0; A[q * np + p] = 0.0; }
-      }
-      for (int e = tid; e < np * half; e += kThreads) {
-        const int i = e / half, t = e % half;
-        const double s = sn[t];
-        if (s == 0.0) continue;
-        const double c = cs[t];
-        const int p = pq[2 * t], q = pq[2 * t + 1];
-        const double vp = V[i * np + p], vq = V[i * np + q];
-        V[i * np + p] = c * vp - s * vq;
-        V[i * np + q] = s * vp + c * vq;
-      }
-      __syncthreads();
+  // 1. tridiagonalisation
+  for (int j = 0; j + 2 < n; ++j) {
+    const int m = n - j - 1;
+    double part = 0.0;
+    for (int i = tid; i < m; i += kThreads) {
+      const double x = A[(j + 1 + i) * pa + j];
+      part += x * x;
     }
-    const int any = flag[0];
+    const double nrm2 = block_sum(part, red);
+    const double x0 = A[(j + 1) * pa + j];
+    if (nrm2 == 0.0) {                     // column already reduced
+      if (tid == 0) { dd[j] = A[j * pa + j]; ee[j] = 0.0; hv[int64_t(n) * n + j] = 0.0; }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = -copysign(sqrt(nrm2), x0);
+    const double beta = 1.0 / (nrm2 - x0 * alpha);       // 2 / (v^T v)
+    for (int i = tid; i < m; i += kThreads) {
+      const double v = (i == 0) ? x0 - alpha : A[(j + 1 + i) * pa + j];
+      vv[i] = v;
+      hv[int64_t(j) * n + i] = v;
+    }
+    if (tid == 0) { dd[j] = A[j * pa + j]; ee[j] = alpha; hv[int64_t(n) * n + j] = beta; }
     __syncthreads();
-    if (!any) break;
+    for (int i = tid; i < m; i += kThreads) {            // p = beta * A_t v
+      const double *row = A + (j + 1 + i) * pa + j + 1;
+      double acc = 0.0;
+      for (int k = 0; k < m; ++k) acc += row[k] * vv[k];
+      pp[i] = beta * acc;
+    }
+    __syncthreads();
+    part = 0.0;
+    for (int i = tid; i < m; i += kThreads) part += vv[i] * pp[i];
+    const double K = 0.5 * beta * block_sum(part, red);
+    for (int i = tid; i < m; i += kThreads) ww[i] = pp[i] - K * vv[i];
+    __syncthreads();
+    for (int e = tid; e < m * m; e += kThreads) {        // A_t -= v w^T + w v^T
+      const int a = e / m, b = e % m;
+      A[(j + 1 + a) * pa + j + 1 + b] -= vv[a] * ww[b] + ww[a] * vv[b];
+    }
+    __syncthreads();
   }
+  if (tid == 0) {
+    if (n >= 2) {
+      dd[n - 2] = A[(n - 2) * pa + n - 2];
+      ee[n - 2] = A[(n - 1) * pa + n - 2];
+    }
+    dd[n - 1] = A[(n - 1) * pa + n - 1];
+    ee[n - 1] = 0.0;
+  }
+  __syncthreads();
 
-  // descending order of the eigenvalues (ties by index)
+  if (tid == 0) { const long long t = wall_clock64(); sc->ticks[0] += t - tph; tph = t; }
+  // 2. implicit QL on T; Z starts as the identity (A is no longer needed). Every wave
+  // holds (d, e) in registers, lane i owning entries i and i + 64, and runs the
+  // sequential recurrence with wave-uniform lane reads and writes.
+  for (int e = tid; e < n * n; e += kThreads) Z[e] = (e / n == e % n) ? 1.0 : 0.0;
+  const int lane = tid & 63;
+  double dlo = lane < n ? dd[lane] : 0.0, dhi = lane + 64 < n ? dd[lane + 64] : 0.0;
+  double elo = lane < n ? ee[lane] : 0.0, ehi = lane + 64 < n ? ee[lane + 64] : 0.0;
+  __syncthreads();
+  auto dget = [&](int i) { return i < 64 ? lane_read(dlo, i) : lane_read(dhi, i - 64); };
+  auto eget = [&](int i) { return i < 64 ? lane_read(elo, i) : lane_read(ehi, i - 64); };
+  auto dset = [&](int i, double v) { if (i < 64) dlo = lane_write(v, i, dlo); else dhi = lane_write(v, i - 64, dhi); };
+  auto eset = [&](int i, double v) { if (i < 64) elo = lane_write(v, i, elo); else ehi = lane_write(v, i - 64, ehi); };
+  const int row = tid;
+  const bool own = row < n;
+  constexpr double kEps = 2.220446049250313e-16;
+  // absolute deflation floor: an off-diagonal below eps*||T|| is negligible at the
+  // absolute accuracy of any backward-stable solver; without it the null space of a
+  // rank-deficient density matrix is iterated to full relative precision
+  double tn = fmax(fmax(fabs(dlo), fabs(dhi)), 2.0 * fmax(fabs(elo), fabs(ehi)));
+  for (int o = 32; o >= 1; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
+  const double efloor = kEps * tn;
+  long long nrot = 0;
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0; iter < 64; ++iter) {
+      // first m >= l with a negligible e[m] (e[n-1] = 0): one ballot per half
+      const double dnl = __shfl_down(dlo, 1, 64), dnh = __shfl_down(dhi, 1, 64);
+      const double dlo1 = lane == 63 ? lane_read(dhi, 0) : dnl;
+      const bool smlo = lane >= l && lane < n - 1 &&
+                        (fabs(elo) <= kEps * (fabs(dlo) + fabs(dlo1)) || fabs(elo) <= efloor);
+      const bool smhi = lane + 64 >= l && lane + 64 < n - 1 &&
+                        (fabs(ehi) <= kEps * (fabs(dhi) + fabs(dnh)) || fabs(ehi) <= efloor);
+      const unsigned long long blo = __ballot(smlo), bhi = __ballot(smhi);
+      int m = n - 1;
+      if (blo) m = __ffsll((long long)blo) - 1;
+      else if (bhi) m = 64 + __ffsll((long long)bhi) - 1;
+      if (m == l) break;
+      const double dl = dget(l), el = eget(l);
+      double g = (dget(l + 1) - dl) / (2.0 * el);
+      double r = sqrt(g * g + 1.0);
+      g = dget(m) - dl + el / (g + copysign(r, g));
+      double s = 1.0, c = 1.0, p = 0.0;
+      double zc = own ? Z[m * n + row] : 0.0;           // current value of column i+1
+      double zn = own ? Z[(m - 1) * n + row] : 0.0;     // column i, fetched one step ahead
+      int i = m - 1;
+      bool split = false;
+      double di1 = dget(m);
+      for (; i >= l; --i) {
+        const double ei = eget(i), di = dget(i);
+        const double zi = zn;
+        if (own && i > l) zn = Z[(i - 1) * n + row];
+        ++nrot;
+        const double f = s * ei, b = c * ei;
+        const double q = f * f + g * g;
+        if (q == 0.0) {                                   // underflow: T splits here
+          eset(i + 1, 0.0);
+          dset(i + 1, di1 - p);
+          eset(m, 0.0);
+          split = true;
+          break;
+        }
+        const double rr = rsqrt_nr(q);                    // 1/sqrt(f^2 + g^2)
+        r = q * rr;
+        eset(i + 1, r);
+        s = f * rr;
+        c = g * rr;
+        g = di1 - p;
+        r = (di - g) * s + 2.0 * c * b;
+        p = s * r;
+        dset(i + 1, g + p);
+        g = c * r - b;
+        di1 = di;
+        if (own) {
+          Z[(i + 1) * n + row] = s * zi + c * zc;
+          zc = c * zi - s * zc;
+        }
+      }
+      if (own) Z[(i + 1) * n + row] = zc;
+      if (split) continue;
+      dset(l, dl - p);
+      eset(l, g);
+      eset(m, 0.0);
+    }
+  }
+  if (wave == 0) {                                        // eigenvalues for the ordering
+    if (lane < n) dd[lane] = dlo;
+    if (lane + 64 < n) dd[lane + 64] = dhi;
+    if (lane == 0) sc->n_rot += nrot;                 // rotation count (diagnostic)
+  }
+  __syncthreads();
+  if (tid == 0) { const long long t = wall_clock64(); sc->ticks[6] += t - tph; tph = t; }
+  // 3. order, keep rule, back-transformation of the kept columns
   for (int i = tid; i < n; i += kThreads) {
-    const double wi = A[i * np + i];
+    const double wi = dd[i];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double wj = A[j * np + j];
+      const double wj = dd[j];
       rank += (wj > wi) || (wj == wi && j < i);
     }
     wsrt[rank] = wi;
@@ -361,11 +468,31 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
   }
   __syncthreads();
   const int k = flag[1];
+  for (int j = n - 3; j >= 0; --j) {                     // z <- H_j z, last reflector first
+    const int m = n - j - 1;
+    const double beta = hv[int64_t(n) * n + j];
+    if (beta == 0.0) continue;
+    for (int i = tid; i < m; i += kThreads) vv[i] = hv[int64_t(j) * n + i];
+    __syncthreads();
+    for (int t = tid; t < k; t += kThreads) {
+      const double *z = Z + isrt[t] * n + j + 1;
+      double acc = 0.0;
+      for (int i = 0; i < m; ++i) acc += vv[i] * z[i];
+      pp[t] = beta * acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < m * k; e += kThreads) {
+      const int t = e / m, i = e % m;
+      Z[isrt[t] * n + j + 1 + i] -= pp[t] * vv[i];
+    }
+    __syncthreads();
+  }
   double *U = ws + op.c;                  // U[j][i], j < k kept vectors, i < n components
   for (int e = tid; e < n * k; e += kThreads) {
     const int j = e / n, i = e % n;
-    U[int64_t(j) * ld + i] = V[i * np + isrt[j]];
+    U[int64_t(j) * ld + i] = Z[isrt[j] * n + i];
   }
+  if (tid == 0) sc->ticks[7] += wall_clock64() - tph;
 }
 
 // ---------------------------------------------------------------- interpreter

@@ -390,10 +390,8 @@ class Builder {
     U.rows = Box{1, 1, {slot}, {int32_t(ucols)}};
     U.cols = L.rows;
     U.ncols = n;
-    const int64_t np = n + (n & 1);
-    bool vglobal = (2 * np * np + 4 * np + 16) > kLdsDoubles;
-    int32_t scratch = -1;
-    if (vglobal) { o.flags |= F_V_GLOBAL; scratch = new_buf(np * np); }
+    o.flags |= F_V_GLOBAL;                    // reflector scratch: n*n + n doubles
+    int32_t scratch = new_buf(n * n + n);
     int32_t id = emit(o);
     refs_.push_back({id, 1, L.buf});
     vb_[L.buf].last = std::max(vb_[L.buf].last, id);

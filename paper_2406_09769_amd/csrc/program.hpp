@@ -24,7 +24,7 @@ enum OpFlags : int32_t {
   F_ACCUM = 4,        // OP_RESCALE: add the exponent to the log accumulator
   F_A_KFAST = 8,      // load A tiles with k varying fastest across threads
   F_B_NFAST = 16,     // load B tiles with n varying fastest across threads
-  F_V_GLOBAL = 32,    // OP_EIG: eigenvector accumulator lives in the workspace
+  F_V_GLOBAL = 32,    // OP_EIG: reflector scratch (n*n + n doubles) at .b
 };
 
 // A two-level index map over a row-major multi-index: off(i) = hi[i / lo_n] + lo[i % lo_n]
@@ -74,6 +74,7 @@ struct NetScalars {
   long long n_learned;
   long long flops;      // executed GEMM flops, 2 m n k at the runtime extents
   long long eig_flops;  // 9 n^3 per density matrix at its runtime dimension
+  long long n_rot;      // Givens rotations of the QL iterations (diagnostic)
   long long ticks[8];   // wall-clock ticks spent per op kind (index = OpKind)
 };
 

@@ -224,9 +224,10 @@ def tn_plan_stats(h: Handle, slices, max_rank: int, env_size: int) -> dict:
 
 
 def tn_profile_last(h: Handle) -> dict:
-    out = (C.c_double * 8)()
+    out = (C.c_double * 9)()
     _check(LIB.tn_profile_last(h.ptr, out))
-    return {"gemm": out[1], "eig": out[2], "rescale": out[3], "scalar": out[4], "ident": out[5]}
+    return {"gemm": out[1], "eig": out[2], "rescale": out[3], "scalar": out[4], "ident": out[5],
+            "eig_reduce": out[0], "eig_ql": out[6], "eig_back": out[7], "ql_rotations": out[8]}
 
 
 def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30) -> np.ndarray:
