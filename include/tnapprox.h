@@ -71,15 +71,19 @@ typedef enum {
   TN_EIG_LEARNED = 1    /* MLP warm start + subspace iteration, exact solve as fallback */
 } tn_eig_mode;
 
+typedef struct tn_model_s *tn_model;      /* warm-start MLP weights on the device */
+typedef struct tn_dataset_s *tn_dataset;  /* harvested (features, leverage) rows on the device */
+
 /* Options; pass NULL for the defaults (FP64, exact eigensolve, tau_rel = 1e-15,
  * tau_deg = 1e-12, the null stream). */
 typedef struct {
   int32_t precision;      /* tn_precision */
   int32_t eig;            /* tn_eig_mode */
-  double residual_tol;    /* learned mode: relative subspace residual accepted (1e-6) */
+  double residual_tol;    /* learned mode: accepted max ||L x - theta x|| / theta_1 (1e-6) */
   double tau_rel;         /* eigenvalues <= tau_rel * w1 are dropped */
   double tau_deg;         /* clusters with gap <= tau_deg * w1 are never split */
   void *hip_stream;       /* hipStream_t the work is queued on (NULL = null stream) */
+  tn_model model;         /* learned mode: the MLP that ranks the warm-start columns */
 } tn_options;
 
 /* Result of one contraction. log_abs = ln|Z| (natural log), sign in {-1, 0, +1};
@@ -92,9 +96,9 @@ typedef struct {
   int64_t flops;          /* algorithmic flops of the executed contractions (sum 2mnk) */
   int64_t eig_flops;      /* nominal eigensolver flops (9 n^3 per density matrix) */
   int64_t n_eig;          /* density matrices diagonalised */
-  int64_t n_fallback;     /* keep() fallbacks (all eigenvalues below the floors) or
-                             learned-mode exact-solve fallbacks */
-  double max_residual;    /* learned mode: largest accepted subspace residual */
+  int64_t n_fallback;     /* keep() fallbacks (all eigenvalues below the floors) */
+  double max_residual;    /* learned mode: largest accepted relative subspace residual */
+  int64_t n_learned;      /* learned mode: density matrices solved by the warm start */
 } tn_result;
 
 typedef struct tn_net_s *tn_net;
@@ -118,6 +122,40 @@ int tn_contract_approx(tn_net net, const tn_path *path, int32_t max_rank,
 int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths,
                              const int32_t *max_ranks, const int32_t *env_sizes, int32_t n,
                              const tn_options *opt, tn_result *outs);
+
+/* ---------------------------------------------------------------- learned warm start
+ * The learned eigensolve (TN_EIG_LEARNED) starts subspace iteration from the columns
+ * of a density matrix L that a small MLP ranks highest, computed row by row from
+ * bond-local features (diagonal and row weight of L, position of the row's bond and
+ * leaf index, size). It accepts the Ritz vectors when every kept residual satisfies
+ * ||L x - theta x|| <= residual_tol * theta_1 and otherwise falls back to the exact
+ * solve (tn_result.n_learned counts the accepted warm starts). Training data come
+ * from the method itself: tn_harvest runs an exact
+ * contraction and records, for every row of every density matrix, its 8 features
+ * and its leverage in the kept subspace (sum over kept vectors of U_ij^2). */
+
+/* A model with Glorot-uniform layers and zero biases drawn from splitmix64(seed). */
+int tn_model_create(uint64_t seed, tn_model *out);
+/* Copy n = 1377 weights in (layout W1[8][32], b1[32], W2[32][32], b2[32], W3[32], b3). */
+int tn_model_set(tn_model m, const float *w, int64_t n);
+int tn_model_get(tn_model m, float *w, int64_t n);
+/* Mean squared error and its gradient for the given rows (rows <= 128, X row-major
+ * rows x 8, y rows), computed by the device training kernel without an update. */
+int tn_model_grad(tn_model m, const float *X, const float *y, int32_t rows, float *grad, double *loss);
+/* steps Adam updates (lr) on minibatches of `batch` rows (<= 128) drawn from ds with
+ * splitmix64(seed); *final_loss is the loss of the last minibatch. */
+int tn_model_train(tn_model m, tn_dataset ds, int32_t steps, int32_t batch, double lr, uint64_t seed,
+                   double *final_loss);
+void tn_model_destroy(tn_model m);
+
+int tn_dataset_create(int64_t capacity_rows, tn_dataset *out);
+/* Rows recorded so far (capped at the capacity). */
+int tn_dataset_size(tn_dataset ds, int64_t *rows);
+int tn_dataset_read(tn_dataset ds, float *X, float *y, int64_t rows);
+void tn_dataset_destroy(tn_dataset ds);
+/* Exact FP64 contraction that also appends training rows to ds. */
+int tn_harvest(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size, tn_dataset ds,
+               tn_result *out);
 
 /* Structural plan for inspection and testing: writes a JSON text with, per
  * partition, the leaf edges in order and the position of every tensor of the
@@ -153,15 +191,23 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
 
 /* U (n x ucols, row-major) = the kept leading eigenvectors of (L + L^T)/2 (n x n),
  * zero columns past the kept rank, under opt's tau_rel and tau_deg (NULL: defaults).
- * n <= 128. *n_fallback is 1 when no eigenvalue survived the rank rule. */
-int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *opt, double *U,
-                 int64_t *n_fallback);
+ * n <= 128. rest = 0: plain rows; rest > 0: rows are (bond, leaf) pairs with leaf
+ * dimension rest (must divide n), the layout the learned warm start reads its row
+ * features from. With opt->eig = TN_EIG_LEARNED and opt->model set, the warm start is
+ * tried first, as in a contraction. stats (8 entries, may be NULL): no eigenvalue
+ * survived the rank rule (0/1), warm start accepted (0/1), kept rank, and the four
+ * rejection counters of tn_profile_last entries 9-12, then 0. */
+int tn_debug_eig(const double *L, int32_t n, int32_t ucols, int32_t rest, const tn_options *opt, double *U,
+                 int64_t *stats);
 
 /* Device time of the last contraction of net, split by op kind: seconds_by_kind[k]
  * for k = 1 GEMM, 2 eigensolve, 3 rescale, 4 closing scalar, 5 identity; inside the
  * eigensolve, 0 = tridiagonal reduction, 6 = QL iteration, 7 = ordering and
- * back-transformation; entry 8 holds the number of QL rotations (9 entries;
- * measured by the first thread of the network's workgroup with the wall clock). */
+ * back-transformation; entry 8 holds the number of QL rotations; entries 9-12 count
+ * the learned warm starts handed to the exact solve because the subspace would not be
+ * smaller than the matrix, every start column was dependent, the weight outside the
+ * subspace could change the cut, or a Ritz residual was too large (13 entries;
+ * times measured by the first thread of the network's workgroup with the wall clock). */
 int tn_profile_last(tn_net net, double *seconds_by_kind);
 
 /* x <- x * 2^-e with e the frexp exponent of max|x|; returns e. */

@@ -85,6 +85,23 @@ struct tn_net_s {
   }
 };
 
+struct tn_model_s {
+  float *d_w = nullptr, *d_m = nullptr, *d_v = nullptr, *d_loss = nullptr;
+  long long t = 0;                 // Adam steps taken
+  ~tn_model_s() {
+    (void)hipFree(d_w); (void)hipFree(d_m); (void)hipFree(d_v); (void)hipFree(d_loss);
+  }
+};
+
+struct tn_dataset_s {
+  float *d_x = nullptr, *d_y = nullptr;
+  int *d_count = nullptr;
+  int64_t cap = 0;
+  ~tn_dataset_s() {
+    (void)hipFree(d_x); (void)hipFree(d_y); (void)hipFree(d_count);
+  }
+};
+
 namespace {
 
 int get_plan(tn_net net, const std::vector<std::vector<int32_t>> &slices, int32_t chi, int32_t env,
@@ -138,7 +155,7 @@ tn_options defaults() {
 
 // Run a list of prepared networks in one interpreter launch.
 int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &plans, const tn_options &o,
-              double *seconds, std::vector<tn::NetScalars> &sc_out) {
+              const tn::KeepParams &kp, double *seconds, std::vector<tn::NetScalars> &sc_out) {
   hipStream_t st = reinterpret_cast<hipStream_t>(o.hip_stream);
   const size_t n = nets.size();
   std::vector<tn::NetDev> nd(n);
@@ -161,7 +178,6 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
   HIP_TRY(hipEventRecord(e0, st));
   HIP_TRY(tn::launch_interp(d_nd, int(n), kp, st));
   HIP_TRY(hipEventRecord(e1, st));
@@ -237,6 +253,10 @@ int tn_create(const tn_tensor *tensors, int32_t n_tensors, const tn_edge *edges,
 
 void tn_destroy(tn_net net) { delete net; }
 
+static int contract_batch(const tn_net *nets, const tn_path *paths, const int32_t *max_ranks,
+                          const int32_t *env_sizes, int32_t n, const tn_options &o, const tn::KeepParams &kp,
+                          tn_result *outs);
+
 int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int32_t *max_ranks,
                              const int32_t *env_sizes, int32_t n, const tn_options *opt, tn_result *outs) {
   g_err.clear();
@@ -247,8 +267,19 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int
   }
   tn_options o = opt ? *opt : defaults();
   if (o.precision != TN_FP64) return fail(TN_EUNSUPPORTED, "precision form not available in this build");
-  if (o.eig != TN_EIG_EXACT) return fail(TN_EUNSUPPORTED, "learned eigensolve not available in this build");
+  if (o.eig != TN_EIG_EXACT && o.eig != TN_EIG_LEARNED) return fail(TN_EINVAL, "unknown eigensolve mode");
+  if (o.eig == TN_EIG_LEARNED && !o.model) return fail(TN_EINVAL, "learned eigensolve needs a model");
+  if (o.eig == TN_EIG_LEARNED && !(o.residual_tol > 0)) return fail(TN_EINVAL, "residual_tol must be > 0");
   if (!(o.tau_rel >= 0) || !(o.tau_deg >= 0)) return fail(TN_EINVAL, "tau_rel and tau_deg must be >= 0");
+  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
+  kp.residual_tol = o.residual_tol;
+  if (o.eig == TN_EIG_LEARNED) kp.model = o.model->d_w;
+  return contract_batch(nets, paths, max_ranks, env_sizes, n, o, kp, outs);
+}
+
+static int contract_batch(const tn_net *nets, const tn_path *paths, const int32_t *max_ranks,
+                          const int32_t *env_sizes, int32_t n, const tn_options &o, const tn::KeepParams &kp,
+                          tn_result *outs) {
   std::vector<tn_net> v(nets, nets + n);
   std::vector<DevPlan *> plans(n);
   for (int32_t i = 0; i < n; ++i) {
@@ -265,7 +296,7 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int
   }
   double secs = 0;
   std::vector<tn::NetScalars> sc;
-  int rc = run_batch(v, plans, o, &secs, sc);
+  int rc = run_batch(v, plans, o, kp, &secs, sc);
   if (rc != TN_OK) return rc;
   for (int32_t i = 0; i < n; ++i) {
     v[i]->last = sc[i];
@@ -284,6 +315,7 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int
     r.n_eig = plans[i]->plan.n_eig;
     r.n_fallback = sc[i].n_fallback;
     r.max_residual = sc[i].max_resid;
+    r.n_learned = sc[i].n_learned;
   }
   return TN_OK;
 }
@@ -329,6 +361,151 @@ int tn_plan_json(const int64_t *dims_flat, const int32_t *orders, int32_t n_tens
   return TN_OK;
 }
 
+// ---------------------------------------------------------------- learned warm start
+
+static uint64_t host_splitmix64(uint64_t &state) {
+  uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int tn_model_create(uint64_t seed, tn_model *out) {
+  g_err.clear();
+  if (!out) return fail(TN_EINVAL, "out is null");
+  *out = nullptr;
+  int rc = check_device();
+  if (rc != TN_OK) return rc;
+  const int P = tn::kMlpParams;
+  std::vector<float> w(P, 0.0f);
+  uint64_t st = seed;
+  auto uni = [&](double lim) { return float((double(host_splitmix64(st) >> 11) * 0x1.0p-53 * 2.0 - 1.0) * lim); };
+  int o = 0;
+  const int shapes[3][2] = {{8, 32}, {32, 32}, {32, 1}};
+  for (auto &sh : shapes) {                 // Glorot-uniform weights, zero biases
+    const double lim = std::sqrt(6.0 / (sh[0] + sh[1]));
+    for (int i = 0; i < sh[0] * sh[1]; ++i) w[o++] = uni(lim);
+    o += sh[1];
+  }
+  auto m = std::make_unique<tn_model_s>();
+  if (hipMalloc(&m->d_w, P * 4) != hipSuccess || hipMalloc(&m->d_m, P * 4) != hipSuccess ||
+      hipMalloc(&m->d_v, P * 4) != hipSuccess || hipMalloc(&m->d_loss, 16) != hipSuccess)
+    return fail(TN_ENOMEM, "model allocation failed");
+  std::vector<float> zero(P, 0.0f);
+  HIP_TRY(hipMemcpy(m->d_w, w.data(), P * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->d_m, zero.data(), P * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->d_v, zero.data(), P * 4, hipMemcpyHostToDevice));
+  *out = m.release();
+  return TN_OK;
+}
+
+int tn_model_set(tn_model m, const float *w, int64_t n) {
+  g_err.clear();
+  if (!m || !w || n != tn::kMlpParams) return fail(TN_EINVAL, "expected 1377 weights");
+  HIP_TRY(hipMemcpy(m->d_w, w, n * 4, hipMemcpyHostToDevice));
+  return TN_OK;
+}
+
+int tn_model_get(tn_model m, float *w, int64_t n) {
+  g_err.clear();
+  if (!m || !w || n != tn::kMlpParams) return fail(TN_EINVAL, "expected 1377 weights");
+  HIP_TRY(hipMemcpy(w, m->d_w, n * 4, hipMemcpyDeviceToHost));
+  return TN_OK;
+}
+
+int tn_model_grad(tn_model m, const float *X, const float *y, int32_t rows, float *grad, double *loss) {
+  g_err.clear();
+  if (!m || !X || !y || !grad || rows < 1 || rows > tn::kMlpBatch) return fail(TN_EINVAL, "1..128 rows expected");
+  float *dx = nullptr, *dy = nullptr, *dg = nullptr;
+  if (hipMalloc(&dx, rows * 8 * 4) != hipSuccess || hipMalloc(&dy, rows * 4) != hipSuccess ||
+      hipMalloc(&dg, tn::kMlpParams * 4) != hipSuccess) {
+    (void)hipFree(dx); (void)hipFree(dy); (void)hipFree(dg);
+    return fail(TN_ENOMEM, "gradient buffers");
+  }
+  hipError_t e = hipMemcpy(dx, X, rows * 8 * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dy, y, rows * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = tn::launch_mlp_train(m->d_w, m->d_m, m->d_v, dx, dy, rows, 1, rows, 0.0f, 0, 0, m->d_loss, dg, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  float l = 0.0f;
+  if (e == hipSuccess) e = hipMemcpy(grad, dg, tn::kMlpParams * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&l, m->d_loss, 4, hipMemcpyDeviceToHost);
+  (void)hipFree(dx); (void)hipFree(dy); (void)hipFree(dg);
+  if (e != hipSuccess) return fail(TN_EDEVICE, std::string("gradient: ") + hipGetErrorString(e));
+  if (loss) *loss = l;
+  return TN_OK;
+}
+
+int tn_model_train(tn_model m, tn_dataset ds, int32_t steps, int32_t batch, double lr, uint64_t seed,
+                   double *final_loss) {
+  g_err.clear();
+  if (!m || !ds || steps < 1 || batch < 1 || batch > tn::kMlpBatch || !(lr > 0)) return fail(TN_EINVAL, "bad training arguments");
+  int cnt = 0;
+  HIP_TRY(hipMemcpy(&cnt, ds->d_count, 4, hipMemcpyDeviceToHost));
+  const int64_t rows = std::min<int64_t>(cnt, ds->cap);
+  if (rows < 1) return fail(TN_EINVAL, "empty dataset");
+  HIP_TRY(tn::launch_mlp_train(m->d_w, m->d_m, m->d_v, ds->d_x, ds->d_y, rows, steps, batch, float(lr), seed, m->t,
+                               m->d_loss, nullptr, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  m->t += steps;
+  float l = 0.0f;
+  HIP_TRY(hipMemcpy(&l, m->d_loss, 4, hipMemcpyDeviceToHost));
+  if (final_loss) *final_loss = l;
+  return TN_OK;
+}
+
+void tn_model_destroy(tn_model m) { delete m; }
+
+int tn_dataset_create(int64_t capacity_rows, tn_dataset *out) {
+  g_err.clear();
+  if (!out || capacity_rows < 1) return fail(TN_EINVAL, "capacity must be >= 1");
+  *out = nullptr;
+  int rc = check_device();
+  if (rc != TN_OK) return rc;
+  auto d = std::make_unique<tn_dataset_s>();
+  d->cap = capacity_rows;
+  if (hipMalloc(&d->d_x, capacity_rows * 8 * 4) != hipSuccess || hipMalloc(&d->d_y, capacity_rows * 4) != hipSuccess ||
+      hipMalloc(&d->d_count, 4) != hipSuccess)
+    return fail(TN_ENOMEM, "dataset allocation failed");
+  int zero = 0;
+  HIP_TRY(hipMemcpy(d->d_count, &zero, 4, hipMemcpyHostToDevice));
+  *out = d.release();
+  return TN_OK;
+}
+
+int tn_dataset_size(tn_dataset ds, int64_t *rows) {
+  g_err.clear();
+  if (!ds || !rows) return fail(TN_EINVAL, "null arguments");
+  int cnt = 0;
+  HIP_TRY(hipMemcpy(&cnt, ds->d_count, 4, hipMemcpyDeviceToHost));
+  *rows = std::min<int64_t>(cnt, ds->cap);
+  return TN_OK;
+}
+
+int tn_dataset_read(tn_dataset ds, float *X, float *y, int64_t rows) {
+  g_err.clear();
+  if (!ds || !X || !y || rows < 0 || rows > ds->cap) return fail(TN_EINVAL, "bad read");
+  if (rows == 0) return TN_OK;
+  HIP_TRY(hipMemcpy(X, ds->d_x, rows * 8 * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(y, ds->d_y, rows * 4, hipMemcpyDeviceToHost));
+  return TN_OK;
+}
+
+void tn_dataset_destroy(tn_dataset ds) { delete ds; }
+
+int tn_harvest(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size, tn_dataset ds, tn_result *out) {
+  g_err.clear();
+  if (!net || !ds || !out) return fail(TN_EINVAL, "null arguments");
+  if (max_rank < 1 || env_size < 1) return fail(TN_EINVAL, "max_rank and env_size must be >= 1");
+  tn_options o = defaults();
+  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
+  kp.hx = ds->d_x;
+  kp.hy = ds->d_y;
+  kp.hcount = ds->d_count;
+  kp.hcap = ds->cap;
+  return contract_batch(&net, path, &max_rank, &env_size, 1, o, kp, out);
+}
+
 // ---------------------------------------------------------------- diagnostics
 
 int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size, int64_t *stats) {
@@ -358,12 +535,15 @@ int tn_profile_last(tn_net net, double *seconds_by_kind) {
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
   for (int k = 0; k < 8; ++k) seconds_by_kind[k] = khz > 0 ? double(net->last.ticks[k]) / (double(khz) * 1e3) : 0.0;
   seconds_by_kind[8] = double(net->last.n_rot);   // QL rotations of the last contraction
+  for (int r = 0; r < 4; ++r) seconds_by_kind[9 + r] = double(net->last.rej[r]);
   return TN_OK;
 }
 
 // Run single device ops on host data through the same interpreter (kernel tests).
+// slots: the kept-rank slots (in: initial extents, default 1; out: as left by the ops).
 static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t> &tab, std::vector<double> &ws,
-                      const std::vector<double> &cst, const tn::KeepParams &kp, tn::NetScalars *sc_out) {
+                      const std::vector<double> &cst, const tn::KeepParams &kp, tn::NetScalars *sc_out,
+                      std::vector<int32_t> *slots_io = nullptr) {
   int rc = check_device();
   if (rc != TN_OK) return rc;
   tn::Op *d_ops = nullptr;
@@ -391,6 +571,8 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
   hipError_t e = hipMemcpy(d_ops, ops.data(), ops.size() * sizeof(tn::Op), hipMemcpyHostToDevice);
   if (e == hipSuccess && !tab.empty()) e = hipMemcpy(d_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice);
   std::vector<int32_t> slots(64, 1);
+  if (slots_io)
+    for (size_t i = 0; i < slots_io->size() && i < slots.size(); ++i) slots[i] = (*slots_io)[i];
   if (e == hipSuccess) e = hipMemcpy(d_ws, slots.data(), 64 * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && !ws.empty()) e = hipMemcpy(d_ws + 32, ws.data(), ws.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess && !cst.empty()) e = hipMemcpy(d_cst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice);
@@ -400,6 +582,10 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess && !ws.empty()) e = hipMemcpy(ws.data(), d_ws + 32, ws.size() * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess && sc_out) e = hipMemcpy(sc_out, d_sc, sizeof(tn::NetScalars), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && slots_io) {
+    e = hipMemcpy(slots.data(), d_ws, 64 * 4, hipMemcpyDeviceToHost);
+    *slots_io = slots;
+  }
   cleanup();
   if (e != hipSuccess) return fail(TN_EDEVICE, std::string("diagnostic run: ") + hipGetErrorString(e));
   return TN_OK;
@@ -449,16 +635,21 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
   return TN_OK;
 }
 
-int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *opt, double *U, int64_t *n_fallback) {
+int tn_debug_eig(const double *L, int32_t n, int32_t ucols, int32_t rest, const tn_options *opt, double *U,
+                 int64_t *stats) {
   g_err.clear();
   if (!L || !U || n < 1 || n > tn::kMaxEigDim || ucols < 1 || ucols > n) return fail(TN_EINVAL, "bad eig arguments");
+  if (rest < 0 || (rest > 0 && (n % rest != 0 || n / rest < 1))) return fail(TN_EINVAL, "rest must divide n");
   tn_options o = opt ? *opt : defaults();
+  if (o.eig == TN_EIG_LEARNED && (!o.model || !(o.residual_tol > 0)))
+    return fail(TN_EINVAL, "learned mode needs a model and residual_tol > 0");
   const int64_t np = n + (n & 1);
   tn::Op op{};
   op.kind = tn::OP_EIG;
   op.count = n;
   op.K = ucols;
-  op.bm = tn::Box{0, n, {0}, {0}};
+  // rows are (bond, leaf) with the bond extent held in kept-rank slot 1, or plain rows
+  op.bm = rest > 0 ? tn::Box{1, rest, {1}, {n / rest}} : tn::Box{0, n, {0}, {0}};
   op.out_dyn = 0;
   op.a = 0;
   int64_t lsz = (int64_t(n) * n + 31) / 32 * 32;
@@ -466,15 +657,28 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, const tn_options *op
   int64_t usz = (int64_t(n) * ucols + 31) / 32 * 32;
   op.b = lsz + usz;
   op.flags |= tn::F_V_GLOBAL;
-  std::vector<double> ws(lsz + usz + np * np + np, 0.0);
+  std::vector<double> ws(lsz + usz + 2 * (np * np + np), 0.0);
   std::memcpy(ws.data(), L, size_t(n) * n * 8);
   tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
+  if (o.eig == TN_EIG_LEARNED) {
+    kp.model = o.model->d_w;
+    kp.residual_tol = o.residual_tol;
+  }
   tn::NetScalars sc{};
-  int rc = run_single({op}, {}, ws, {}, kp, &sc);
+  std::vector<int32_t> slots(2, 1);
+  if (rest > 0) slots[1] = n / rest;
+  int rc = run_single({op}, {}, ws, {}, kp, &sc, &slots);
   if (rc != TN_OK) return rc;
-  for (int32_t i = 0; i < n; ++i)          // device layout U[j][i] -> host n x ucols
-    for (int32_t j = 0; j < ucols; ++j) U[int64_t(i) * ucols + j] = ws[lsz + int64_t(j) * n + i];
-  if (n_fallback) *n_fallback = sc.n_fallback;
+  const int32_t k = slots[0];
+  for (int32_t i = 0; i < n; ++i)          // device layout U[j][i] -> host n x ucols, zero past k
+    for (int32_t j = 0; j < ucols; ++j) U[int64_t(i) * ucols + j] = j < k ? ws[lsz + int64_t(j) * n + i] : 0.0;
+  if (stats) {
+    stats[0] = sc.n_fallback;
+    stats[1] = sc.n_learned;
+    stats[2] = k;
+    for (int r = 0; r < 4; ++r) stats[3 + r] = sc.rej[r];
+    stats[7] = 0;
+  }
   return TN_OK;
 }
 

@@ -261,44 +261,49 @@ __device__ void ident_wg(double *x, int64_t d) {
 
 // ---------------------------------------------------------------- eigensolver
 
-// Symmetric eigensolve of the density matrix and the keep rule.
-//  1. Householder reduction to tridiagonal form T = Q^T A Q in LDS (256 threads);
-//     the reflectors go to the op's workspace scratch for the back-transformation.
-//  2. Implicit QL with shifts on T, accumulating the rotations into Z (T = Z W Z^T).
-//     The scalar recurrence is sequential, so every wave runs it on its own copy of
-//     (d, e) without barriers and each thread applies the rotations to its row of Z.
-//  3. Eigenvalues sorted in descending order, the keep rule picks k, and only the k
-//     kept columns of Z are transformed back with the reflectors: U = Q Z_kept.
-__device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
-                         double *lds) {
-  const int ld = int(op.count);            // static dimension = row stride of L and of U
-  const int n = box_eff(op.bm);            // runtime dimension: the valid leading block
-  const int ucols = op.K;
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const int pa = n + 1;                    // odd LDS pitch of A: conflict-free row access
-  double *A = lds;                         // n x pa during the reduction, then Z (column-major n x n)
-  double *Z = lds;
-  double *vv = lds + n * pa;               // Householder vector of the current step
-  double *pp = vv + n;
-  double *ww = pp + n;
-  double *dd = ww + n;                     // diagonal of T
-  double *ee = dd + n;                     // off-diagonal of T (ee[n-1] = 0)
-  double *dW = ee + n;                     // per-wave copies of (d, e): 4 x 2n
-  double *wsrt = dW + 8 * n;               // eigenvalues, descending
-  int *isrt = reinterpret_cast<int *>(wsrt + n);
-  int *flag = isrt + n + (n & 1);
-  double *red = reinterpret_cast<double *>(flag + 4);
-  double *hv = ws + op.b;                  // reflectors: v_j at hv[j*n + i], beta_j at hv[n*n + j]
-  const double *L = ws + op.a;
+// ---------------------------------------------------------------- dense symmetric eigensolve
+//
+// Householder reduction to tridiagonal form T = Q^T A Q in LDS (256 threads; the
+// reflectors go to global scratch), implicit QL with shifts on T accumulating the
+// rotations into Z (every wave runs the sequential recurrence on lane-distributed
+// (d, e) registers; each thread rotates its own row of Z), descending order, and a
+// back-transformation U = Q Z of only the kept columns.
 
+struct EigWs {          // LDS work area of one solve of order n
+  double *A;            // n x pa matrix, then Z (column-major n x n)
+  double *vv, *pp, *ww, *dd, *ee, *wsrt;
+  int *isrt, *flag;
+  double *red;
+  double *hv;           // reflectors in global memory: v_j at hv[j*n + i], beta_j at hv[n*n + j]
+  int n, pa;
+};
+
+__host__ __device__ constexpr int eig_lds_doubles(int n) { return n * (n + 1) + 6 * n + (n + 1) / 2 + 8; }
+
+__device__ EigWs eig_ws(double *base, int n, double *hv) {
+  EigWs E;
+  E.n = n;
+  E.pa = n + 1;                        // odd pitch: conflict-free row access
+  E.A = base;
+  E.vv = base + n * E.pa;
+  E.pp = E.vv + n;
+  E.ww = E.pp + n;
+  E.dd = E.ww + n;
+  E.ee = E.dd + n;
+  E.wsrt = E.ee + n;
+  E.isrt = reinterpret_cast<int *>(E.wsrt + n);
+  E.flag = E.isrt + n + (n & 1);
+  E.red = reinterpret_cast<double *>(E.flag + 4);
+  E.hv = hv;
+  return E;
+}
+
+// Tridiagonalise E.A (symmetric, loaded) and diagonalise T by implicit QL.
+// On return Z (column-major) overwrites E.A and the eigenvalues are in E.dd.
+__device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
+  const int n = E.n, pa = E.pa, tid = threadIdx.x, wave = tid >> 6;
+  double *A = E.A, *vv = E.vv, *pp = E.pp, *ww = E.ww, *dd = E.dd, *ee = E.ee, *hv = E.hv;
   long long tph = wall_clock64();
-  for (int e = tid; e < n * n; e += kThreads) {
-    const int i = e / n, j = e % n;
-    A[i * pa + j] = 0.5 * (L[int64_t(i) * ld + j] + L[int64_t(j) * ld + i]);
-  }
-  __syncthreads();
-
-  // 1. tridiagonalisation
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;
     double part = 0.0;
@@ -306,7 +311,7 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
       const double x = A[(j + 1 + i) * pa + j];
       part += x * x;
     }
-    const double nrm2 = block_sum(part, red);
+    const double nrm2 = block_sum(part, E.red);
     const double x0 = A[(j + 1) * pa + j];
     if (nrm2 == 0.0) {                     // column already reduced
       if (tid == 0) { dd[j] = A[j * pa + j]; ee[j] = 0.0; hv[int64_t(n) * n + j] = 0.0; }
@@ -331,7 +336,7 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
     __syncthreads();
     part = 0.0;
     for (int i = tid; i < m; i += kThreads) part += vv[i] * pp[i];
-    const double K = 0.5 * beta * block_sum(part, red);
+    const double K = 0.5 * beta * block_sum(part, E.red);
     for (int i = tid; i < m; i += kThreads) ww[i] = pp[i] - K * vv[i];
     __syncthreads();
     for (int e = tid; e < m * m; e += kThreads) {        // A_t -= v w^T + w v^T
@@ -349,11 +354,9 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
     ee[n - 1] = 0.0;
   }
   __syncthreads();
+  if (timed && tid == 0) { const long long t = wall_clock64(); sc->ticks[0] += t - tph; tph = t; }
 
-  if (tid == 0) { const long long t = wall_clock64(); sc->ticks[0] += t - tph; tph = t; }
-  // 2. implicit QL on T; Z starts as the identity (A is no longer needed). Every wave
-  // holds (d, e) in registers, lane i owning entries i and i + 64, and runs the
-  // sequential recurrence with wave-uniform lane reads and writes.
+  double *Z = A;
   for (int e = tid; e < n * n; e += kThreads) Z[e] = (e / n == e % n) ? 1.0 : 0.0;
   const int lane = tid & 63;
   double dlo = lane < n ? dd[lane] : 0.0, dhi = lane + 64 < n ? dd[lane + 64] : 0.0;
@@ -437,62 +440,401 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
   if (wave == 0) {                                        // eigenvalues for the ordering
     if (lane < n) dd[lane] = dlo;
     if (lane + 64 < n) dd[lane + 64] = dhi;
-    if (lane == 0) sc->n_rot += nrot;                 // rotation count (diagnostic)
+    if (lane == 0) sc->n_rot += nrot;
   }
   __syncthreads();
-  if (tid == 0) { const long long t = wall_clock64(); sc->ticks[6] += t - tph; tph = t; }
-  // 3. order, keep rule, back-transformation of the kept columns
-  for (int i = tid; i < n; i += kThreads) {
-    const double wi = dd[i];
+  if (timed && tid == 0) sc->ticks[6] += wall_clock64() - tph;
+}
+
+// descending order of E.dd into E.wsrt / E.isrt (ties by index)
+__device__ void order_desc(const EigWs &E) {
+  const int n = E.n;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const double wi = E.dd[i];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double wj = dd[j];
+      const double wj = E.dd[j];
       rank += (wj > wi) || (wj == wi && j < i);
     }
-    wsrt[rank] = wi;
-    isrt[rank] = i;
+    E.wsrt[rank] = wi;
+    E.isrt[rank] = i;
   }
   __syncthreads();
-  if (tid == 0) {
-    const double w1 = wsrt[0];
-    int k = ucols < n ? ucols : n;
-    while (k >= 1 && wsrt[k - 1] <= kp.tau_rel * w1) --k;
-    while (k >= 1 && k < n && wsrt[k] > kp.floor * w1 && wsrt[k - 1] - wsrt[k] <= kp.tau_deg * w1) --k;
-    if (k == 0) {
-      k = ucols < n ? ucols : n;
-      sc->n_fallback += 1;
-    }
-    flag[1] = k;
-    dyn[op.out_dyn] = k;
-    sc->eig_flops += 9LL * n * n * n;
-  }
-  __syncthreads();
-  const int k = flag[1];
-  for (int j = n - 3; j >= 0; --j) {                     // z <- H_j z, last reflector first
+}
+
+// The rank rule on descending eigenvalues w[0..navail) of a matrix of order n:
+// at most ucols, drop w <= tau_rel*w1, never split a cluster (gap <= tau_deg*w1)
+// whose lower member exceeds floor*w1. Returns 0 if nothing survives.
+__device__ int keep_rank(const double *w, int navail, int n, int ucols, const KeepParams &kp) {
+  const double w1 = w[0];
+  int k = ucols < n ? ucols : n;
+  if (k > navail) k = navail;
+  while (k >= 1 && w[k - 1] <= kp.tau_rel * w1) --k;
+  while (k >= 1 && k < navail && w[k] > kp.floor * w1 && w[k - 1] - w[k] <= kp.tau_deg * w1) --k;
+  return k;
+}
+
+// z <- Q z for the k kept columns of Z (E.isrt[0..k)), last reflector first
+__device__ void back_transform(const EigWs &E, int k) {
+  const int n = E.n, tid = threadIdx.x;
+  double *Z = E.A;
+  for (int j = n - 3; j >= 0; --j) {
     const int m = n - j - 1;
-    const double beta = hv[int64_t(n) * n + j];
+    const double beta = E.hv[int64_t(n) * n + j];
     if (beta == 0.0) continue;
-    for (int i = tid; i < m; i += kThreads) vv[i] = hv[int64_t(j) * n + i];
+    for (int i = tid; i < m; i += kThreads) E.vv[i] = E.hv[int64_t(j) * n + i];
     __syncthreads();
     for (int t = tid; t < k; t += kThreads) {
-      const double *z = Z + isrt[t] * n + j + 1;
+      const double *z = Z + E.isrt[t] * n + j + 1;
       double acc = 0.0;
-      for (int i = 0; i < m; ++i) acc += vv[i] * z[i];
-      pp[t] = beta * acc;
+      for (int i = 0; i < m; ++i) acc += E.vv[i] * z[i];
+      E.pp[t] = beta * acc;
     }
     __syncthreads();
     for (int e = tid; e < m * k; e += kThreads) {
       const int t = e / m, i = e % m;
-      Z[isrt[t] * n + j + 1 + i] -= pp[t] * vv[i];
+      Z[E.isrt[t] * n + j + 1 + i] -= E.pp[t] * E.vv[i];
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------- learned warm start
+
+constexpr int kF = 8, kH1 = 32, kH2 = 32;
+constexpr int kNParams = kF * kH1 + kH1 + kH1 * kH2 + kH2 + kH2 + 1;
+
+// Row statistics of L (valid n x n block, row stride ld): diag max, trace, ||L||_F^2.
+struct RowStats { double dmax, tr, fro2; };
+
+__device__ RowStats row_stats(const double *L, int ld, int n, double *red) {
+  double dm = 0.0, tr = 0.0, f2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const double d = L[int64_t(i) * ld + i];
+    dm = fmax(dm, d);
+    tr += d;
+  }
+  for (int e = threadIdx.x; e < n * n; e += kThreads) {
+    const double v = L[int64_t(e / n) * ld + e % n];
+    f2 += v * v;
+  }
+  RowStats s;
+  s.dmax = block_max(dm, red);
+  s.tr = block_sum(tr, red);
+  s.fro2 = block_sum(f2, red);
+  return s;
+}
+
+// Bond-local features of row i (same definition as the reference in numpy).
+__device__ void row_features(const double *L, int ld, int n, int i, int rest, bool bonded, const RowStats &st,
+                             float *f) {
+  const double d = L[int64_t(i) * ld + i];
+  double rn2 = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double v = L[int64_t(i) * ld + j];
+    rn2 += v * v;
+  }
+  const double rel = st.dmax > 0.0 ? d / st.dmax : 0.0;
+  f[0] = float(rel);
+  f[1] = float(log10(fmax(rel, 1e-30)) / 15.0);
+  f[2] = float(st.tr > 0.0 ? d / st.tr : 0.0);
+  f[3] = float(st.fro2 > 0.0 ? sqrt(rn2 / st.fro2) : 0.0);
+  f[4] = float((d > 0.0 && st.tr > 0.0) ? rn2 / (d * st.tr) : 0.0);
+  if (bonded) {
+    const int nb = n / rest;
+    f[5] = float(double(i / rest) / double(nb > 1 ? nb - 1 : 1));
+    f[6] = float(double(i % rest) / double(rest > 1 ? rest - 1 : 1));
+  } else {
+    f[5] = float(double(i) / double(n > 1 ? n - 1 : 1));
+    f[6] = 0.0f;
+  }
+  f[7] = float(n / 128.0);
+}
+
+// MLP 8 -> 32 -> 32 -> 1 (tanh, tanh, logistic); w laid out as W1 (8x32), b1, W2 (32x32), b2, W3, b3.
+// Each first-layer unit is folded into the second layer's sums as soon as it is known,
+// so only those 32 sums stay live.
+__device__ float mlp_score(const float *w, const float *f) {
+  const float *W1 = w, *b1 = W1 + kF * kH1, *W2 = b1 + kH1, *b2 = W2 + kH1 * kH2, *W3 = b2 + kH2, *b3 = W3 + kH2;
+  float z2[kH2];
+#pragma unroll
+  for (int j = 0; j < kH2; ++j) z2[j] = b2[j];
+  for (int a = 0; a < kH1; ++a) {
+    float z = b1[a];
+#pragma unroll
+    for (int c = 0; c < kF; ++c) z += f[c] * W1[c * kH1 + a];
+    const float h = tanhf(z);
+#pragma unroll
+    for (int j = 0; j < kH2; ++j) z2[j] += h * W2[a * kH2 + j];
+  }
+  float z = b3[0];
+#pragma unroll
+  for (int j = 0; j < kH2; ++j) z += tanhf(z2[j]) * W3[j];
+  return 1.0f / (1.0f + expf(-z));
+}
+
+// Columns of V (n x p, row pitch p, in LDS) orthonormalised in order by classical
+// Gram-Schmidt applied twice. A column whose part outside the span of the earlier ones
+// has squared norm <= kDropRel times its own (zero columns included) becomes zero: the
+// basis keeps its width and the zero directions give Ritz values 0, which the keep
+// rule discards. Returns the number of nonzero columns.
+constexpr double kDropRel = 1e-26;
+__device__ int orth_drop(double *V, int n, int p, double *coef, double *red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int alive = 0;
+  for (int j = 0; j < p; ++j) {
+    double part = 0.0;
+    for (int i = tid; i < n; i += kThreads) { const double v = V[i * p + j]; part += v * v; }
+    const double nv2 = block_sum(part, red);
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = wave; q < j; q += kThreads / 64) {   // c_q = V_q . V_j, one wave per q
+        double acc = 0.0;
+        for (int i = lane; i < n; i += 64) acc += V[i * p + q] * V[i * p + j];
+        acc = wave_sum(acc);
+        if (lane == 0) coef[q] = acc;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += kThreads) {
+        double v = V[i * p + j];
+        for (int q = 0; q < j; ++q) v -= coef[q] * V[i * p + q];
+        V[i * p + j] = v;
+      }
+      __syncthreads();
+    }
+    part = 0.0;
+    for (int i = tid; i < n; i += kThreads) { const double v = V[i * p + j]; part += v * v; }
+    const double nu2 = block_sum(part, red);
+    const bool keep = nv2 > 0.0 && nu2 > kDropRel * nv2;
+    const double scale = keep ? 1.0 / sqrt(nu2) : 0.0;
+    for (int i = tid; i < n; i += kThreads) V[i * p + j] *= scale;
+    __syncthreads();
+    alive += keep ? 1 : 0;
+  }
+  return alive;
+}
+
+// W = A V (A: n x pa symmetric in LDS, V: n x p)
+__device__ void sym_times(const double *A, int pa, const double *V, int n, int p, double *W) {
+  for (int e = threadIdx.x; e < n * p; e += kThreads) {
+    const int i = e / p, c = e % p;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += A[i * pa + j] * V[j * p + c];
+    W[e] = acc;
+  }
+  __syncthreads();
+}
+
+// Learned warm start. The MLP scores the rows of L; the columns of L at the p best
+// scores, orthonormalised (orth_drop), start a subspace iteration V <- orth(L V) with
+// Rayleigh-Ritz on H = V^T L V, W = L V. The keep rule runs on the Ritz values. With
+// P = V V^T and C = (I-P) L (I-P), the largest eigenvalue of L off span(V) is at most
+// b = min(t, f): t = tr(L) - tr(H) = tr(C) (C is PSD when L is), and
+// f = sqrt(||L||^2 - 2||W||^2 + ||H||^2 + slack) = ||C||_F (Frobenius identities of
+// the 2x2 block split; the slack covers their rounding). The result is accepted when
+//  * the weight off span(V) is negligible, t <= kLearnedTail * theta_1, or the rank is
+//    capped by max_rank and b cannot move that cut (b <= theta_k / 2 and
+//    b < theta_k - tau_deg * theta_1), and
+//  * every kept Ritz pair has ||L x - theta x|| <= residual_tol * theta_1.
+// Returns true with U written and the kept rank set; false leaves everything for the
+// exact solve (the reason is counted in sc->rej).
+constexpr double kLearnedTail = 1e-11, kFroSlack = 1e-13;
+__device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
+                            double *lds, int n, int ld, int ucols) {
+  const int tid = threadIdx.x;
+  const bool bonded = op.bm.nd > 0;
+  const int rest = op.bm.rest;
+  const int kprev = bonded ? n / rest : n;
+  int p = (bonded && kprev < ucols ? kprev : ucols) + 4;
+  if (p > n - 1) p = n - 1;
+  const int pa = n + 1;
+  // LDS: A (n x pa) | V (n x p) | W (n x p) | G (p x p) | eig of H | weights (floats) | scores, sel
+  double *A = lds;
+  double *V = A + n * pa;
+  double *W = V + n * p;
+  double *G = W + n * p;
+  double *gd = G + p * p;
+  double *Hb = gd + p + 1;
+  float *wts = reinterpret_cast<float *>(Hb + eig_lds_doubles(p));
+  float *score = wts + kNParams + 1;
+  int *sel = reinterpret_cast<int *>(score + n + 1);
+  int *flag = sel + n + 1;
+  double *red = reinterpret_cast<double *>(flag + 4 + 2);
+  const int need = int((reinterpret_cast<char *>(red + 8) - reinterpret_cast<char *>(lds)) / 8);
+  if (n < 16 || p < 2 || 4 * p > 3 * n || need > kLdsDoubles) {   // no saving over the full solve
+    if (tid == 0) sc->rej[0] += 1;
+    return false;
+  }
+  const double *L = ws + op.a;
+  for (int e = tid; e < n * n; e += kThreads) {
+    const int i = e / n, j = e % n;
+    A[i * pa + j] = 0.5 * (L[int64_t(i) * ld + j] + L[int64_t(j) * ld + i]);
+  }
+  for (int e = tid; e < kNParams; e += kThreads) wts[e] = kp.model[e];
+  const RowStats st = row_stats(L, ld, n, red);
+  for (int i = tid; i < n; i += kThreads) {
+    float f[kF];
+    row_features(L, ld, n, i, rest, bonded, st, f);
+    const float sc_i = mlp_score(wts, f);
+    score[i] = sc_i == sc_i ? sc_i : -1.0f;              // a NaN score ranks last
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kThreads) {              // the p best-scored rows
+    const float si = score[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += (score[j] > si) || (score[j] == si && j < i);
+    if (rank < p) sel[rank] = i;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * p; e += kThreads) V[e] = A[(e / p) * pa + sel[e % p]];
+  __syncthreads();
+  if (orth_drop(V, n, p, gd, red) == 0) {
+    if (tid == 0) sc->rej[1] += 1;
+    return false;
+  }
+  double part = 0.0;
+  for (int i = tid; i < n; i += kThreads) part += A[i * pa + i];
+  const double trL = block_sum(part, red);
+  const double fro2L = st.fro2;
+  double *hv2 = ws + op.b + int64_t(n) * n + n;          // reflectors of the p x p solve
+  const int kmax = ucols < n ? ucols : n;
+  int why = 2;
+  for (int it = 0; it < 3; ++it) {
+    sym_times(A, pa, V, n, p, W);                        // W = L V
+    EigWs E = eig_ws(Hb, p, hv2);
+    for (int e = tid; e < p * p; e += kThreads) {        // H = V^T W (symmetrised)
+      const int a = e / p, b = e % p;
+      double h1 = 0.0, h2 = 0.0;
+      for (int i = 0; i < n; ++i) { h1 += V[i * p + a] * W[i * p + b]; h2 += V[i * p + b] * W[i * p + a]; }
+      E.A[a * E.pa + b] = 0.5 * (h1 + h2);
+    }
+    __syncthreads();
+    part = 0.0;
+    double pw = 0.0, ph = 0.0;
+    for (int a = tid; a < p; a += kThreads) part += E.A[a * E.pa + a];
+    for (int e = tid; e < n * p; e += kThreads) pw += W[e] * W[e];
+    for (int e = tid; e < p * p; e += kThreads) { const double h = E.A[(e / p) * E.pa + e % p]; ph += h * h; }
+    const double trH = block_sum(part, red);
+    const double fro2W = block_sum(pw, red);
+    const double fro2H = block_sum(ph, red);
+    tri_ql(E, sc, false);
+    order_desc(E);
+    if (tid == 0) flag[2] = keep_rank(E.wsrt, p, n, ucols, kp);
+    __syncthreads();
+    const int k = flag[2];
+    const double th1 = E.wsrt[0];
+    const double tail = fmax(trL - trH, 0.0);
+    const double fro = sqrt(fmax(fro2L - 2.0 * fro2W + fro2H, 0.0) + kFroSlack * fro2L);
+    const double bnd = fmin(tail, fro);
+    bool cut_ok = k >= 1 && th1 > 0.0;
+    if (cut_ok) {
+      const double thk = E.wsrt[k - 1];
+      cut_ok = tail <= kLearnedTail * th1 || (k == kmax && bnd <= 0.5 * thk && bnd < thk - kp.tau_deg * th1);
+    }
+    if (cut_ok) {
+      back_transform(E, k);                              // Y columns (p x k) in E.A
+      // Ritz vectors x_j = V y_j (written to U) and residual norms |W y_j - theta_j x_j|
+      for (int j = tid; j < k; j += kThreads) G[j] = 0.0;
+      __syncthreads();
+      double *U = ws + op.c;
+      for (int e = tid; e < n * k; e += kThreads) {
+        const int i = e / k, j = e % k;
+        const double *y = E.A + E.isrt[j] * p;
+        double x = 0.0, wy = 0.0;
+        for (int c = 0; c < p; ++c) { x += V[i * p + c] * y[c]; wy += W[i * p + c] * y[c]; }
+        const double r = wy - E.wsrt[j] * x;
+        atomicAdd(&G[j], r * r);
+        U[int64_t(j) * ld + i] = x;
+      }
+      __syncthreads();
+      double rmax = 0.0;
+      for (int j = tid; j < k; j += kThreads) rmax = fmax(rmax, sqrt(G[j]));
+      rmax = block_max(rmax, red);
+      if (rmax <= kp.residual_tol * th1) {
+        if (tid == 0) {
+          dyn[op.out_dyn] = k;
+          sc->n_learned += 1;
+          sc->max_resid = fmax(sc->max_resid, rmax / th1);
+          sc->eig_flops += 9LL * p * p * p + 4LL * n * n * p * (it + 1);
+        }
+        __syncthreads();
+        return true;
+      }
+      why = 3;
+    } else {
+      why = 2;
+    }
+    if (it == 2) break;
+    __syncthreads();
+    for (int e = tid; e < n * p; e += kThreads) V[e] = W[e];   // one more step: V <- orth(L V)
+    __syncthreads();
+    if (orth_drop(V, n, p, gd, red) == 0) { why = 1; break; }
+  }
+  if (tid == 0) sc->rej[why] += 1;
+  __syncthreads();
+  return false;
+}
+
+// Harvest (features, leverage) rows of a solved density matrix for training.
+__device__ void harvest_rows(const Op &op, const double *ws, int n, int ld, int k, const KeepParams &kp,
+                             double *red, int *slot) {
+  const double *L = ws + op.a, *U = ws + op.c;
+  const bool bonded = op.bm.nd > 0;
+  const int rest = op.bm.rest;
+  const RowStats st = row_stats(L, ld, n, red);
+  if (threadIdx.x == 0) slot[0] = atomicAdd(kp.hcount, n);
+  __syncthreads();
+  const long long base = slot[0];
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    if (base + i >= kp.hcap) continue;
+    float f[kF];
+    row_features(L, ld, n, i, rest, bonded, st, f);
+    double lev = 0.0;
+    for (int j = 0; j < k; ++j) lev += U[int64_t(j) * ld + i] * U[int64_t(j) * ld + i];
+    for (int a = 0; a < kF; ++a) kp.hx[(base + i) * kF + a] = f[a];
+    kp.hy[base + i] = float(lev);
+  }
+  __syncthreads();
+}
+
+__device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
+                         double *lds) {
+  const int ld = int(op.count);            // static dimension = row stride of L and of U
+  const int n = box_eff(op.bm);            // runtime dimension: the valid leading block
+  const int ucols = op.K;
+  const int tid = threadIdx.x;
+  if (kp.model && eig_learned(op, ws, dyn, kp, sc, lds, n, ld, ucols)) return;
+  EigWs E = eig_ws(lds, n, ws + op.b);
+  const double *L = ws + op.a;
+  long long t0 = wall_clock64();
+  for (int e = tid; e < n * n; e += kThreads) {
+    const int i = e / n, j = e % n;
+    E.A[i * E.pa + j] = 0.5 * (L[int64_t(i) * ld + j] + L[int64_t(j) * ld + i]);
+  }
+  __syncthreads();
+  tri_ql(E, sc, true);
+  t0 = wall_clock64();
+  order_desc(E);
+  if (tid == 0) {
+    int k = keep_rank(E.wsrt, n, n, ucols, kp);
+    if (k == 0) {
+      k = ucols < n ? ucols : n;
+      sc->n_fallback += 1;
+    }
+    E.flag[1] = k;
+    dyn[op.out_dyn] = k;
+    sc->eig_flops += 9LL * n * n * n;
+  }
+  __syncthreads();
+  const int k = E.flag[1];
+  back_transform(E, k);
   double *U = ws + op.c;                  // U[j][i], j < k kept vectors, i < n components
   for (int e = tid; e < n * k; e += kThreads) {
     const int j = e / n, i = e % n;
-    U[int64_t(j) * ld + i] = Z[isrt[j] * n + i];
+    U[int64_t(j) * ld + i] = E.A[E.isrt[j] * n + i];
   }
-  if (tid == 0) sc->ticks[7] += wall_clock64() - tph;
+  __syncthreads();
+  if (kp.hx) harvest_rows(op, ws, n, ld, k, kp, E.red, E.flag + 2);
+  if (tid == 0) sc->ticks[7] += wall_clock64() - t0;
 }
 
 // ---------------------------------------------------------------- interpreter

@@ -23,9 +23,20 @@ struct KeepParams {
   double tau_rel;
   double tau_deg;
   double floor;
+  double residual_tol;     // learned mode: accepted max ||L x - theta x|| / theta_1
+  const float *model;      // learned mode: MLP weights, or null for the exact solve
+  float *hx, *hy;          // harvest: feature rows (8 floats) and leverage targets, or null
+  int *hcount;             // harvest: rows written so far (atomic)
+  long long hcap;          // harvest: capacity in rows
 };
 
 constexpr double kClusterFloor = 1e-10;
+constexpr int kMlpParams = 8 * 32 + 32 + 32 * 32 + 32 + 32 + 1;   // 8 -> 32 -> 32 -> 1
+constexpr int kMlpBatch = 128;                                  // rows per training step (max)
+
+hipError_t launch_mlp_train(float *w, float *m, float *v, const float *X, const float *Y, long long nrows, int steps,
+                            int batch, float lr, unsigned long long seed, long long t0, float *loss_out,
+                            float *grad_out, hipStream_t stream);
 
 hipError_t launch_interp(const NetDev *nets_dev, int n_nets, const KeepParams &kp, hipStream_t stream);
 

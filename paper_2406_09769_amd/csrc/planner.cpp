@@ -390,8 +390,8 @@ class Builder {
     U.rows = Box{1, 1, {slot}, {int32_t(ucols)}};
     U.cols = L.rows;
     U.ncols = n;
-    o.flags |= F_V_GLOBAL;                    // reflector scratch: n*n + n doubles
-    int32_t scratch = new_buf(n * n + n);
+    o.flags |= F_V_GLOBAL;                    // reflector scratch: n x n solve, then p x p solve
+    int32_t scratch = new_buf(2 * (n * n + n));
     int32_t id = emit(o);
     refs_.push_back({id, 1, L.buf});
     vb_[L.buf].last = std::max(vb_[L.buf].last, id);

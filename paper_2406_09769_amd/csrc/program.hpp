@@ -24,7 +24,7 @@ enum OpFlags : int32_t {
   F_ACCUM = 4,        // OP_RESCALE: add the exponent to the log accumulator
   F_A_KFAST = 8,      // load A tiles with k varying fastest across threads
   F_B_NFAST = 16,     // load B tiles with n varying fastest across threads
-  F_V_GLOBAL = 32,    // OP_EIG: reflector scratch (n*n + n doubles) at .b
+  F_V_GLOBAL = 32,    // OP_EIG: reflector scratch (2 (n*n + n) doubles) at .b
 };
 
 // A two-level index map over a row-major multi-index: off(i) = hi[i / lo_n] + lo[i % lo_n]
@@ -75,6 +75,8 @@ struct NetScalars {
   long long flops;      // executed GEMM flops, 2 m n k at the runtime extents
   long long eig_flops;  // 9 n^3 per density matrix at its runtime dimension
   long long n_rot;      // Givens rotations of the QL iterations (diagnostic)
+  long long rej[4];     // learned warm starts handed to the exact solve, by reason:
+                        // subspace too large for n, lost every column, cut not certified, residual
   long long ticks[8];   // wall-clock ticks spent per op kind (index = OpKind)
 };
 

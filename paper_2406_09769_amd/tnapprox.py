@@ -42,13 +42,15 @@ class tn_path(C.Structure):
 
 class tn_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eig", C.c_int32), ("residual_tol", C.c_double),
-                ("tau_rel", C.c_double), ("tau_deg", C.c_double), ("hip_stream", C.c_void_p)]
+                ("tau_rel", C.c_double), ("tau_deg", C.c_double), ("hip_stream", C.c_void_p),
+                ("model", C.c_void_p)]
 
 
 class tn_result(C.Structure):
     _fields_ = [("log_abs", C.c_double), ("sign", C.c_int32), ("_pad", C.c_int32),
                 ("seconds", C.c_double), ("flops", C.c_int64), ("eig_flops", C.c_int64),
-                ("n_eig", C.c_int64), ("n_fallback", C.c_int64), ("max_residual", C.c_double)]
+                ("n_eig", C.c_int64), ("n_fallback", C.c_int64), ("max_residual", C.c_double),
+                ("n_learned", C.c_int64)]
 
 
 def _load():
@@ -70,10 +72,23 @@ def _load():
         "tn_plan_stats": (C.c_int, [C.c_void_p, P(tn_path), C.c_int32, C.c_int32, P(C.c_int64)]),
         "tn_debug_gemm": (C.c_int, [P(C.c_double), C.c_int64, C.c_int64, P(C.c_double), C.c_int64, C.c_int64,
                                     P(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
-        "tn_debug_eig": (C.c_int, [P(C.c_double), C.c_int32, C.c_int32, P(tn_options), P(C.c_double),
-                                   P(C.c_int64)]),
+        "tn_debug_eig": (C.c_int, [P(C.c_double), C.c_int32, C.c_int32, C.c_int32, P(tn_options),
+                                   P(C.c_double), P(C.c_int64)]),
         "tn_debug_rescale": (C.c_int, [P(C.c_double), C.c_int64, P(C.c_int64)]),
         "tn_profile_last": (C.c_int, [C.c_void_p, P(C.c_double)]),
+        "tn_model_create": (C.c_int, [C.c_uint64, P(C.c_void_p)]),
+        "tn_model_set": (C.c_int, [C.c_void_p, P(C.c_float), C.c_int64]),
+        "tn_model_get": (C.c_int, [C.c_void_p, P(C.c_float), C.c_int64]),
+        "tn_model_grad": (C.c_int, [C.c_void_p, P(C.c_float), P(C.c_float), C.c_int32, P(C.c_float),
+                                    P(C.c_double)]),
+        "tn_model_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_uint64,
+                                     P(C.c_double)]),
+        "tn_model_destroy": (None, [C.c_void_p]),
+        "tn_dataset_create": (C.c_int, [C.c_int64, P(C.c_void_p)]),
+        "tn_dataset_size": (C.c_int, [C.c_void_p, P(C.c_int64)]),
+        "tn_dataset_read": (C.c_int, [C.c_void_p, P(C.c_float), P(C.c_float), C.c_int64]),
+        "tn_dataset_destroy": (None, [C.c_void_p]),
+        "tn_harvest": (C.c_int, [C.c_void_p, P(tn_path), C.c_int32, C.c_int32, C.c_void_p, P(tn_result)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -130,9 +145,9 @@ class _PathArgs:
 
 
 def _options(precision=TN_FP64, eig=TN_EIG_EXACT, residual_tol=1e-6, tau_rel=1e-15, tau_deg=1e-12,
-             stream=None):
+             stream=None, model=None):
     return tn_options(int(precision), int(eig), float(residual_tol), float(tau_rel), float(tau_deg),
-                      C.c_void_p(stream) if stream else None)
+                      C.c_void_p(stream) if stream else None, model.ptr if model is not None else None)
 
 
 @dataclass
@@ -145,10 +160,12 @@ class Result:
     n_eig: int
     n_fallback: int
     max_residual: float
+    n_learned: int
 
 
 def _result(r: tn_result) -> Result:
-    return Result(r.log_abs, r.sign, r.seconds, r.flops, r.eig_flops, r.n_eig, r.n_fallback, r.max_residual)
+    return Result(r.log_abs, r.sign, r.seconds, r.flops, r.eig_flops, r.n_eig, r.n_fallback, r.max_residual,
+                  r.n_learned)
 
 
 # ---------------------------------------------------------------- the calls
@@ -224,10 +241,12 @@ def tn_plan_stats(h: Handle, slices, max_rank: int, env_size: int) -> dict:
 
 
 def tn_profile_last(h: Handle) -> dict:
-    out = (C.c_double * 9)()
+    out = (C.c_double * 13)()
     _check(LIB.tn_profile_last(h.ptr, out))
     return {"gemm": out[1], "eig": out[2], "rescale": out[3], "scalar": out[4], "ident": out[5],
-            "eig_reduce": out[0], "eig_ql": out[6], "eig_back": out[7], "ql_rotations": out[8]}
+            "eig_reduce": out[0], "eig_ql": out[6], "eig_back": out[7], "ql_rotations": out[8],
+            "learned_rejected": {"size": int(out[9]), "dependent": int(out[10]), "cut": int(out[11]),
+                                 "residual": int(out[12])}}
 
 
 def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30) -> np.ndarray:
@@ -243,14 +262,20 @@ def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30) -> np.n
     return Cm
 
 
-def tn_debug_eig(L: np.ndarray, ucols: int, tau_rel=1e-15, tau_deg=1e-12):
+def tn_debug_eig(L: np.ndarray, ucols: int, tau_rel=1e-15, tau_deg=1e-12, rest: int = 0, model=None,
+                 residual_tol=1e-6, stats: bool = False):
+    """Kept eigenvectors (n x ucols, zero past the kept rank) and the fallback flag;
+    with stats=True also the dict of the learned warm start's outcome."""
     L = np.ascontiguousarray(L, dtype=np.float64)
     n = L.shape[0]
     U = np.zeros((n, ucols))
-    fb = C.c_int64(0)
-    o = _options(tau_rel=tau_rel, tau_deg=tau_deg)
-    _check(LIB.tn_debug_eig(_dptr(L), n, int(ucols), C.byref(o), _dptr(U), C.byref(fb)))
-    return U, int(fb.value)
+    st = (C.c_int64 * 8)()
+    o = _options(tau_rel=tau_rel, tau_deg=tau_deg, residual_tol=residual_tol,
+                 eig=TN_EIG_LEARNED if model is not None else TN_EIG_EXACT, model=model)
+    _check(LIB.tn_debug_eig(_dptr(L), n, int(ucols), int(rest), C.byref(o), _dptr(U), st))
+    if not stats:
+        return U, int(st[0])
+    return U, int(st[0]), {"learned": int(st[1]), "kept": int(st[2]), "rejected": [int(x) for x in st[3:7]]}
 
 
 def tn_debug_rescale(x: np.ndarray):
@@ -258,6 +283,82 @@ def tn_debug_rescale(x: np.ndarray):
     e = C.c_int64(0)
     _check(LIB.tn_debug_rescale(_dptr(x), x.size, C.byref(e)))
     return x, int(e.value)
+
+
+# ---------------------------------------------------------------- learned warm start
+
+N_PARAMS = 8 * 32 + 32 + 32 * 32 + 32 + 32 + 1
+
+
+class Model:
+    """Owns a tn_model (the warm-start MLP on the device)."""
+
+    def __init__(self, seed: int = 0):
+        self.ptr = C.c_void_p()
+        _check(LIB.tn_model_create(C.c_uint64(seed), C.byref(self.ptr)))
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            LIB.tn_model_destroy(self.ptr)
+            self.ptr = None
+
+    def set(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(LIB.tn_model_set(self.ptr, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+
+    def get(self):
+        w = np.zeros(N_PARAMS, dtype=np.float32)
+        _check(LIB.tn_model_get(self.ptr, w.ctypes.data_as(C.POINTER(C.c_float)), N_PARAMS))
+        return w
+
+    def grad(self, X, y):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        g = np.zeros(N_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        fp = C.POINTER(C.c_float)
+        _check(LIB.tn_model_grad(self.ptr, X.ctypes.data_as(fp), y.ctypes.data_as(fp), len(y), g.ctypes.data_as(fp),
+                                 C.byref(loss)))
+        return loss.value, g
+
+    def train(self, ds, steps: int, batch: int = 128, lr: float = 3e-3, seed: int = 1) -> float:
+        loss = C.c_double()
+        _check(LIB.tn_model_train(self.ptr, ds.ptr, int(steps), int(batch), float(lr), C.c_uint64(seed),
+                                  C.byref(loss)))
+        return loss.value
+
+
+class Dataset:
+    """Owns a tn_dataset (harvested training rows on the device)."""
+
+    def __init__(self, capacity: int):
+        self.ptr = C.c_void_p()
+        _check(LIB.tn_dataset_create(int(capacity), C.byref(self.ptr)))
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            LIB.tn_dataset_destroy(self.ptr)
+            self.ptr = None
+
+    def size(self) -> int:
+        n = C.c_int64()
+        _check(LIB.tn_dataset_size(self.ptr, C.byref(n)))
+        return n.value
+
+    def read(self):
+        n = self.size()
+        X = np.zeros((n, 8), dtype=np.float32)
+        y = np.zeros(n, dtype=np.float32)
+        fp = C.POINTER(C.c_float)
+        _check(LIB.tn_dataset_read(self.ptr, X.ctypes.data_as(fp), y.ctypes.data_as(fp), n))
+        return X, y
+
+
+def tn_harvest(h: Handle, slices, max_rank: int, env_size: int, ds: Dataset) -> Result:
+    p = _PathArgs(slices)
+    r = tn_result()
+    _check(LIB.tn_harvest(h.ptr, C.byref(p.path), int(max_rank), int(env_size), ds.ptr, C.byref(r)))
+    return _result(r)
 
 
 # ---------------------------------------------------------------- conveniences

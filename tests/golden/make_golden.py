@@ -1,13 +1,16 @@
 """Write oracle values for the full-size workloads into tests/golden/*.json.
 
 Calls only oracle/ (and the seeded input generators). Usage:
-    python tests/golden/make_golden.py w2        # 64x64 2D Ising, 8 betas x chi {32,64} x env {1,2}
+    python tests/golden/make_golden.py w2   # 64x64 2D Ising, 8 betas x chi {32,64} x env {1,2}
+    python tests/golden/make_golden.py w4   # 64 signed-J random 3-regular graphs, beta 1, chi 64
+    python tests/golden/make_golden.py w5   # 32 random 3-SAT #CSP formulas, n 150, m 450, chi 32
 """
 import json
 import math
 import os
 import sys
 import time
+from multiprocessing import Pool
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -34,7 +37,35 @@ def w2(out_path):
                "rows": rows}, open(out_path, "w"), indent=1)
 
 
+def _one(args):
+    kind, i, chi = args
+    net = inputs.rrg_batch(i + 1)[i] if kind == "w4" else inputs.csp_batch(i + 1)[i]
+    t = time.time()
+    st = dm.Stats()
+    v, s = dm.contract_approx(net, chi, 1, stats=st)
+    row = {"index": i, "name": net.name, "n_sites": net.n_sites, "n_tensors": len(net.tensors),
+           "chi": chi, "env": 1, "log_abs": v, "sign": s, "n_eig": st.n_eig, "seconds": time.time() - t}
+    print(json.dumps(row), flush=True)
+    return row
+
+
+def batch(kind, count, chi, out_path, workers=4):
+    with Pool(workers) as pool:
+        rows = sorted(pool.map(_one, [(kind, i, chi) for i in range(count)]), key=lambda r: r["index"])
+    desc = {"w4": ("64 signed-J random 3-regular graphs, n_i = 2*U{50..150}, J ~ N(0,1), beta 1, "
+                   "seed 4000+i, greedy path", "paper_2406_09769_amd.inputs.rrg_batch(64)"),
+            "w5": ("32 random 3-SAT #CSP formulas, n 150, m 450, seed 5000+i, greedy path",
+                   "paper_2406_09769_amd.inputs.csp_batch(32)")}[kind]
+    json.dump({"workload": desc[0], "generator": desc[1],
+               "oracle": f"oracle.dm.contract_approx(net, {chi}, 1) with default cutoffs",
+               "rows": rows}, open(out_path, "w"), indent=1)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "w2"
     if which == "w2":
         w2(os.path.join(HERE, "w2_oracle.json"))
+    elif which == "w4":
+        batch("w4", 64, 64, os.path.join(HERE, "w4_oracle.json"))
+    elif which == "w5":
+        batch("w5", 32, 32, os.path.join(HERE, "w5_oracle.json"))
