@@ -206,8 +206,10 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, int32_t rest, const 
  * back-transformation; entry 8 holds the number of QL rotations; entries 9-12 count
  * the learned warm starts handed to the exact solve because the subspace would not be
  * smaller than the matrix, every start column was dependent, the weight outside the
- * subspace could change the cut, or a Ritz residual was too large (13 entries;
- * times measured by the first thread of the network's workgroup with the wall clock). */
+ * subspace could change the cut, or a Ritz residual was too large; entries 13-16 split
+ * the time of the warm starts (accepted or not) into scoring and start basis, products
+ * with L, the small eigensolve, and Ritz vectors with residuals (17 entries; times
+ * measured by the first thread of the network's workgroup with the wall clock). */
 int tn_profile_last(tn_net net, double *seconds_by_kind);
 
 /* x <- x * 2^-e with e the frexp exponent of max|x|; returns e. */

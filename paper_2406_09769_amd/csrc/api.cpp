@@ -536,6 +536,8 @@ int tn_profile_last(tn_net net, double *seconds_by_kind) {
   for (int k = 0; k < 8; ++k) seconds_by_kind[k] = khz > 0 ? double(net->last.ticks[k]) / (double(khz) * 1e3) : 0.0;
   seconds_by_kind[8] = double(net->last.n_rot);   // QL rotations of the last contraction
   for (int r = 0; r < 4; ++r) seconds_by_kind[9 + r] = double(net->last.rej[r]);
+  for (int r = 0; r < 4; ++r)
+    seconds_by_kind[13 + r] = khz > 0 ? double(net->last.lticks[r]) / (double(khz) * 1e3) : 0.0;
   return TN_OK;
 }
 

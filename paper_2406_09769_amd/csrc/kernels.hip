@@ -164,6 +164,151 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
   }
 }
 
+// Pipelined GEMM for ops whose row, column and k offsets fit in LDS. The output is
+// cut into MB x NB blocks (4 waves, each TM x TN MFMA tiles of 16 x 16) and K into
+// chunks of KC; the (block, chunk) steps run as one flat sequence with two LDS
+// buffers: while the waves multiply step s out of one buffer, every thread already
+// holds its loads of step s+1 (possibly the next block) in registers. Offsets are
+// resolved once per op into LDS: kA/kB (k), rA (A row), cB (B column), rC/cC (C).
+template <int MB, int NB, int KC, int TM, int TN>
+__device__ void gemm_piped(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
+                           double *__restrict__ C, double *lds, int M, int N, int K, const int32_t *kA,
+                           const int32_t *kB, const int32_t *rA, const int32_t *cB, const int32_t *rC,
+                           const int32_t *cC) {
+  constexpr int WN = NB / (16 * TN);               // waves along N
+  static_assert((MB / (16 * TM)) * WN == 4, "4 waves per block");
+  constexpr int PA = MB + 1, PB = NB + 1;          // LDS pitches of a k row
+  constexpr int SA = KC * PA, SB = KC * PB;        // one stage
+  constexpr int LA = (MB * KC + kThreads - 1) / kThreads;
+  constexpr int LB = (KC * NB + kThreads - 1) / kThreads;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const bool akf = (op.flags & F_A_KFAST) != 0;
+  const bool bnf = (op.flags & F_B_NFAST) != 0;
+  const int nbm = (M + MB - 1) / MB, nbn = (N + NB - 1) / NB, nch = (K + KC - 1) / KC;
+  const int steps = nbm * nbn * nch;
+  double ra[LA], rb[LB];
+  auto load = [&](int s) {
+    const int blk = s / nch, ch = s - blk * nch;
+    const int m0 = (blk / nbn) * MB, n0 = (blk % nbn) * NB, k0 = ch * KC;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + kThreads * q;
+      const int i = akf ? e / KC : e % MB, k = akf ? e % KC : e / MB;
+      double x = 0.0;
+      if (e < MB * KC && m0 + i < M && k0 + k < K) x = A[int64_t(rA[m0 + i]) + kA[k0 + k]];
+      ra[q] = x;
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + kThreads * q;
+      const int j = bnf ? e % NB : e / KC, k = bnf ? e / NB : e % KC;
+      double y = 0.0;
+      if (e < KC * NB && n0 + j < N && k0 + k < K) y = B[int64_t(cB[n0 + j]) + kB[k0 + k]];
+      rb[q] = y;
+    }
+  };
+  auto stash = [&](int buf) {
+    double *as = lds + buf * (SA + SB), *bs = as + SA;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + kThreads * q;
+      const int i = akf ? e / KC : e % MB, k = akf ? e % KC : e / MB;
+      if (e < MB * KC) as[k * PA + i] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + kThreads * q;
+      const int j = bnf ? e % NB : e / KC, k = bnf ? e / NB : e % KC;
+      if (e < KC * NB) bs[k * PB + j] = rb[q];
+    }
+  };
+  v4d acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  if (steps > 0) load(0);
+  for (int s = 0; s < steps; ++s) {
+    const int buf = s & 1;
+    stash(buf);
+    __syncthreads();
+    if (s + 1 < steps) load(s + 1);                // in flight during the MFMAs
+    const int blk = s / nch, ch = s - blk * nch;
+    const int kc = K - ch * KC < KC ? K - ch * KC : KC;
+    const double *as = lds + buf * (SA + SB) + wm * TM * 16 + (lane & 15);
+    const double *bs = lds + buf * (SA + SB) + SA + wn * TN * 16 + (lane & 15);
+    for (int kk = 0; kk < kc; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = as[kr * PA + a * 16];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = bs[kr * PB + b * 16];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (ch == nch - 1) {                           // block done: write it out
+      const int m0 = (blk / nbn) * MB, n0 = (blk % nbn) * NB;
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = m0 + wm * TM * 16 + a * 16 + (lane >> 4) + 4 * r;   // D: lane l, reg r = row l/16 + 4r
+            const int col = n0 + wn * TN * 16 + b * 16 + (lane & 15);
+            if (row < M && col < N) C[int64_t(rC[row]) + cC[col]] = acc[a][b][r];
+          }
+          acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// LDS doubles of the two stages of a gemm_piped configuration
+constexpr int piped_stage_doubles(int MB, int NB, int KC) { return 2 * (KC * (MB + 1) + KC * (NB + 1)); }
+constexpr int kPipedTiles = piped_stage_doubles(32, 128, 32);   // the largest configuration below
+
+// One GEMM op. Returns false when its offsets do not fit the LDS cache (the caller
+// then runs gemm_tiles).
+__device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
+                        double *__restrict__ C, const int32_t *__restrict__ tab, double *lds, NetScalars *sc) {
+  const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
+  const int64_t NS = op.bn.n;
+  if (2 * (int64_t(M) + N + K) > 2 * int64_t(kLdsDoubles - kPipedTiles)) return false;
+  int32_t *kA = reinterpret_cast<int32_t *>(lds + kPipedTiles);
+  int32_t *kB = kA + K, *rA = kB + K, *rC = rA + M, *cB = rC + M, *cC = cB + N;
+  const int tid = threadIdx.x;
+  if (tid == 0) sc->flops += 2LL * M * N * K;
+  for (int k = tid; k < K; k += kThreads) {
+    const int ks = box_conv(op.bk_, k);
+    kA[k] = tab[op.ak + ks];
+    kB[k] = tab[op.bk + ks];
+  }
+  for (int m = tid; m < M; m += kThreads) {
+    const int sm = box_conv(op.bm, m);
+    rA[m] = int32_t(map_off(tab, op.am, sm));
+    rC[m] = int32_t(sm * NS);
+  }
+  for (int n = tid; n < N; n += kThreads) {
+    const int sn = box_conv(op.bnb, n);
+    cB[n] = int32_t(map_off(tab, op.bn, sn));
+    cC[n] = sn;
+  }
+  __syncthreads();
+  if (M <= 16)
+    gemm_piped<16, 512, 8, 1, 8>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC);
+  else if (M <= 32)
+    gemm_piped<32, 128, 32, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC);
+  else
+    gemm_piped<64, 64, 32, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC);
+  return true;
+}
+
 // ---------------------------------------------------------------- lane access
 
 // value of v in lane `src` (src wave-uniform), as a wave-uniform scalar
@@ -664,6 +809,10 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
     if (tid == 0) sc->rej[0] += 1;
     return false;
   }
+  long long tl = wall_clock64();
+  auto lap = [&](int slot) {
+    if (tid == 0) { const long long t = wall_clock64(); sc->lticks[slot] += t - tl; tl = t; }
+  };
   const double *L = ws + op.a;
   for (int e = tid; e < n * n; e += kThreads) {
     const int i = e / n, j = e % n;
@@ -687,7 +836,9 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
   __syncthreads();
   for (int e = tid; e < n * p; e += kThreads) V[e] = A[(e / p) * pa + sel[e % p]];
   __syncthreads();
-  if (orth_drop(V, n, p, gd, red) == 0) {
+  const int alive0 = orth_drop(V, n, p, gd, red);
+  lap(0);
+  if (alive0 == 0) {
     if (tid == 0) sc->rej[1] += 1;
     return false;
   }
@@ -716,10 +867,12 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
     const double trH = block_sum(part, red);
     const double fro2W = block_sum(pw, red);
     const double fro2H = block_sum(ph, red);
+    lap(1);
     tri_ql(E, sc, false);
     order_desc(E);
     if (tid == 0) flag[2] = keep_rank(E.wsrt, p, n, ucols, kp);
     __syncthreads();
+    lap(2);
     const int k = flag[2];
     const double th1 = E.wsrt[0];
     const double tail = fmax(trL - trH, 0.0);
@@ -749,6 +902,7 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
       double rmax = 0.0;
       for (int j = tid; j < k; j += kThreads) rmax = fmax(rmax, sqrt(G[j]));
       rmax = block_max(rmax, red);
+      lap(3);
       if (rmax <= kp.residual_tol * th1) {
         if (tid == 0) {
           dyn[op.out_dyn] = k;
@@ -767,7 +921,9 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
     __syncthreads();
     for (int e = tid; e < n * p; e += kThreads) V[e] = W[e];   // one more step: V <- orth(L V)
     __syncthreads();
-    if (orth_drop(V, n, p, gd, red) == 0) { why = 1; break; }
+    const int alive = orth_drop(V, n, p, gd, red);
+    lap(0);
+    if (alive == 0) { why = 1; break; }
   }
   if (tid == 0) sc->rej[why] += 1;
   __syncthreads();
@@ -862,7 +1018,8 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
       case OP_GEMM: {
         const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
         const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-        gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1, nd.sc);
+        if (!gemm_op(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc))
+          gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1, nd.sc);
         break;
       }
       case OP_EIG:

@@ -77,6 +77,8 @@ struct NetScalars {
   long long n_rot;      // Givens rotations of the QL iterations (diagnostic)
   long long rej[4];     // learned warm starts handed to the exact solve, by reason:
                         // subspace too large for n, lost every column, cut not certified, residual
+  long long lticks[4];  // learned warm start, wall-clock ticks: scoring and start basis,
+                        // products with L and norms, the small eigensolve, Ritz vectors
   long long ticks[8];   // wall-clock ticks spent per op kind (index = OpKind)
 };
 

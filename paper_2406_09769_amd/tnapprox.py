@@ -241,12 +241,13 @@ def tn_plan_stats(h: Handle, slices, max_rank: int, env_size: int) -> dict:
 
 
 def tn_profile_last(h: Handle) -> dict:
-    out = (C.c_double * 13)()
+    out = (C.c_double * 17)()
     _check(LIB.tn_profile_last(h.ptr, out))
     return {"gemm": out[1], "eig": out[2], "rescale": out[3], "scalar": out[4], "ident": out[5],
             "eig_reduce": out[0], "eig_ql": out[6], "eig_back": out[7], "ql_rotations": out[8],
             "learned_rejected": {"size": int(out[9]), "dependent": int(out[10]), "cut": int(out[11]),
-                                 "residual": int(out[12])}}
+                                 "residual": int(out[12])},
+            "learned_time": {"start": out[13], "products": out[14], "small_eig": out[15], "ritz": out[16]}}
 
 
 def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30) -> np.ndarray:
