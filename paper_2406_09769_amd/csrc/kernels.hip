@@ -419,11 +419,13 @@ struct EigWs {          // LDS work area of one solve of order n
   double *vv, *pp, *ww, *dd, *ee, *wsrt;
   int *isrt, *flag;
   double *red;
+  double *wq;           // per wave: its own copy of the tridiagonal (d then e, 2n doubles)
   double *hv;           // reflectors in global memory: v_j at hv[j*n + i], beta_j at hv[n*n + j]
   int n, pa;
 };
 
-__host__ __device__ constexpr int eig_lds_doubles(int n) { return n * (n + 1) + 6 * n + (n + 1) / 2 + 8; }
+__host__ __device__ constexpr int eig_lds_doubles(int n) { return n * (n + 1) + 14 * n + (n + 1) / 2 + 8; }
+static_assert(eig_lds_doubles(128) <= kLdsDoubles, "the largest density matrix fits LDS");
 
 __device__ EigWs eig_ws(double *base, int n, double *hv) {
   EigWs E;
@@ -439,6 +441,7 @@ __device__ EigWs eig_ws(double *base, int n, double *hv) {
   E.isrt = reinterpret_cast<int *>(E.wsrt + n);
   E.flag = E.isrt + n + (n & 1);
   E.red = reinterpret_cast<double *>(E.flag + 4);
+  E.wq = E.red + 4;
   E.hv = hv;
   return E;
 }
@@ -504,89 +507,89 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
   double *Z = A;
   for (int e = tid; e < n * n; e += kThreads) Z[e] = (e / n == e % n) ? 1.0 : 0.0;
   const int lane = tid & 63;
-  double dlo = lane < n ? dd[lane] : 0.0, dhi = lane + 64 < n ? dd[lane + 64] : 0.0;
-  double elo = lane < n ? ee[lane] : 0.0, ehi = lane + 64 < n ? ee[lane + 64] : 0.0;
+  // Every wave that owns rows of Z (and wave 0, whose copy yields the eigenvalues)
+  // runs the same chase on a private copy of (d, e) in LDS, so no barrier is needed
+  // inside the iteration. Within a sweep step i reads d[i], e[i] and writes index
+  // i+1, so the reads of the next step are issued one step ahead.
+  double *wd = E.wq + 2 * n * wave, *we = wd + n;
+  for (int i = lane; i < n; i += 64) { wd[i] = dd[i]; we[i] = ee[i]; }
   __syncthreads();
-  auto dget = [&](int i) { return i < 64 ? lane_read(dlo, i) : lane_read(dhi, i - 64); };
-  auto eget = [&](int i) { return i < 64 ? lane_read(elo, i) : lane_read(ehi, i - 64); };
-  auto dset = [&](int i, double v) { if (i < 64) dlo = lane_write(v, i, dlo); else dhi = lane_write(v, i - 64, dhi); };
-  auto eset = [&](int i, double v) { if (i < 64) elo = lane_write(v, i, elo); else ehi = lane_write(v, i - 64, ehi); };
   const int row = tid;
   const bool own = row < n;
   constexpr double kEps = 2.220446049250313e-16;
-  // absolute deflation floor: an off-diagonal below eps*||T|| is negligible at the
-  // absolute accuracy of any backward-stable solver; without it the null space of a
-  // rank-deficient density matrix is iterated to full relative precision
-  double tn = fmax(fmax(fabs(dlo), fabs(dhi)), 2.0 * fmax(fabs(elo), fabs(ehi)));
-  for (int o = 32; o >= 1; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
-  const double efloor = kEps * tn;
   long long nrot = 0;
-  for (int l = 0; l < n; ++l) {
-    for (int iter = 0; iter < 64; ++iter) {
-      // first m >= l with a negligible e[m] (e[n-1] = 0): one ballot per half
-      const double dnl = __shfl_down(dlo, 1, 64), dnh = __shfl_down(dhi, 1, 64);
-      const double dlo1 = lane == 63 ? lane_read(dhi, 0) : dnl;
-      const bool smlo = lane >= l && lane < n - 1 &&
-                        (fabs(elo) <= kEps * (fabs(dlo) + fabs(dlo1)) || fabs(elo) <= efloor);
-      const bool smhi = lane + 64 >= l && lane + 64 < n - 1 &&
-                        (fabs(ehi) <= kEps * (fabs(dhi) + fabs(dnh)) || fabs(ehi) <= efloor);
-      const unsigned long long blo = __ballot(smlo), bhi = __ballot(smhi);
-      int m = n - 1;
-      if (blo) m = __ffsll((long long)blo) - 1;
-      else if (bhi) m = 64 + __ffsll((long long)bhi) - 1;
-      if (m == l) break;
-      const double dl = dget(l), el = eget(l);
-      double g = (dget(l + 1) - dl) / (2.0 * el);
-      double r = sqrt(g * g + 1.0);
-      g = dget(m) - dl + el / (g + copysign(r, g));
-      double s = 1.0, c = 1.0, p = 0.0;
-      double zc = own ? Z[m * n + row] : 0.0;           // current value of column i+1
-      double zn = own ? Z[(m - 1) * n + row] : 0.0;     // column i, fetched one step ahead
-      int i = m - 1;
-      bool split = false;
-      double di1 = dget(m);
-      for (; i >= l; --i) {
-        const double ei = eget(i), di = dget(i);
-        const double zi = zn;
-        if (own && i > l) zn = Z[(i - 1) * n + row];
-        ++nrot;
-        const double f = s * ei, b = c * ei;
-        const double q = f * f + g * g;
-        if (q == 0.0) {                                   // underflow: T splits here
-          eset(i + 1, 0.0);
-          dset(i + 1, di1 - p);
-          eset(m, 0.0);
-          split = true;
-          break;
+  if (wave == 0 || wave * 64 < n) {
+    // absolute deflation floor: an off-diagonal below eps*||T|| is negligible at the
+    // absolute accuracy of any backward-stable solver; without it the null space of a
+    // rank-deficient density matrix is iterated to full relative precision
+    double tn = 0.0;
+    for (int i = lane; i < n; i += 64) tn = fmax(tn, fmax(fabs(wd[i]), 2.0 * fabs(we[i])));
+    const double efloor = kEps * wave_max(tn);
+    for (int l = 0; l < n; ++l) {
+      for (int iter = 0; iter < 64; ++iter) {
+        int m = n - 1;                               // first m >= l with a negligible e[m]
+        for (int base = l; base < n - 1; base += 64) {
+          const int i = base + lane;
+          bool small = false;
+          if (i < n - 1) {
+            const double ei = fabs(we[i]);
+            small = ei <= kEps * (fabs(wd[i]) + fabs(wd[i + 1])) || ei <= efloor;
+          }
+          const unsigned long long bl = __ballot(small);
+          if (bl) { m = base + __ffsll((long long)bl) - 1; break; }
         }
-        const double rr = rsqrt_nr(q);                    // 1/sqrt(f^2 + g^2)
-        r = q * rr;
-        eset(i + 1, r);
-        s = f * rr;
-        c = g * rr;
-        g = di1 - p;
-        r = (di - g) * s + 2.0 * c * b;
-        p = s * r;
-        dset(i + 1, g + p);
-        g = c * r - b;
-        di1 = di;
-        if (own) {
-          Z[(i + 1) * n + row] = s * zi + c * zc;
-          zc = c * zi - s * zc;
+        if (m == l) break;
+        const double dl = wd[l], el = we[l];
+        double g = (wd[l + 1] - dl) / (2.0 * el);
+        double r = sqrt(g * g + 1.0);
+        g = wd[m] - dl + el / (g + copysign(r, g));
+        double s = 1.0, c = 1.0, p = 0.0;
+        double zc = own ? Z[m * n + row] : 0.0;       // current value of column i+1
+        double zn = own ? Z[(m - 1) * n + row] : 0.0; // column i, fetched one step ahead
+        double di1 = wd[m];
+        double en = we[m - 1], dn = wd[m - 1];        // e[i], d[i], fetched one step ahead
+        int i = m - 1;
+        bool split = false;
+        for (; i >= l; --i) {
+          const double ei = en, di = dn, zi = zn;
+          if (i > l) {
+            en = we[i - 1];
+            dn = wd[i - 1];
+            if (own) zn = Z[(i - 1) * n + row];
+          }
+          ++nrot;
+          const double f = s * ei, b = c * ei;
+          const double q = f * f + g * g;
+          if (q == 0.0) {                                // underflow: T splits here
+            if (lane == 0) { we[i + 1] = 0.0; wd[i + 1] = di1 - p; we[m] = 0.0; }
+            split = true;
+            break;
+          }
+          const double rr = rsqrt_nr(q);                // 1/sqrt(f^2 + g^2)
+          r = q * rr;
+          s = f * rr;
+          c = g * rr;
+          g = di1 - p;
+          const double t = (di - g) * s + 2.0 * c * b;
+          p = s * t;
+          const double dnew = g + p;
+          g = c * t - b;
+          if (lane == 0) { we[i + 1] = r; wd[i + 1] = dnew; }
+          di1 = di;
+          if (own) {
+            Z[(i + 1) * n + row] = s * zi + c * zc;
+            zc = c * zi - s * zc;
+          }
         }
+        if (own) Z[(i + 1) * n + row] = zc;
+        if (split) continue;
+        if (lane == 0) { wd[l] = dl - p; we[l] = g; we[m] = 0.0; }
       }
-      if (own) Z[(i + 1) * n + row] = zc;
-      if (split) continue;
-      dset(l, dl - p);
-      eset(l, g);
-      eset(m, 0.0);
     }
   }
-  if (wave == 0) {                                        // eigenvalues for the ordering
-    if (lane < n) dd[lane] = dlo;
-    if (lane + 64 < n) dd[lane + 64] = dhi;
-    if (lane == 0) sc->n_rot += nrot;
-  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kThreads) dd[i] = E.wq[i];     // wave 0's eigenvalues
+  if (tid == 0) sc->n_rot += nrot;
   __syncthreads();
   if (timed && tid == 0) sc->ticks[6] += wall_clock64() - tph;
 }
