@@ -452,17 +452,30 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
   const int n = E.n, pa = E.pa, tid = threadIdx.x, wave = tid >> 6;
   double *A = E.A, *vv = E.vv, *pp = E.pp, *ww = E.ww, *dd = E.dd, *ee = E.ee, *hv = E.hv;
   long long tph = wall_clock64();
+  // Householder reduction, three barriers per column. The norm of the next column
+  // below the diagonal is summed while the trailing update writes it; the 2-sided
+  // update uses w = p - K v without storing w: A -= v p^T + p v^T - 2K v v^T.
+  // Matrix-vector products run 4 lanes per row with two partial sums per lane.
+  const int lane = tid & 63, sub = tid & 3, grp = tid >> 2;
+  double *rs = E.wq, *rs2 = E.wq + 4;                  // per-wave partial sums (free until QL)
+  bool have_norm = false;
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;
-    double part = 0.0;
-    for (int i = tid; i < m; i += kThreads) {
-      const double x = A[(j + 1 + i) * pa + j];
-      part += x * x;
+    double nrm2;
+    if (have_norm) {
+      nrm2 = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+    } else {
+      double part = 0.0;
+      for (int i = tid; i < m; i += kThreads) {
+        const double x = A[(j + 1 + i) * pa + j];
+        part += x * x;
+      }
+      nrm2 = block_sum(part, E.red);
     }
-    const double nrm2 = block_sum(part, E.red);
     const double x0 = A[(j + 1) * pa + j];
     if (nrm2 == 0.0) {                     // column already reduced
       if (tid == 0) { dd[j] = A[j * pa + j]; ee[j] = 0.0; hv[int64_t(n) * n + j] = 0.0; }
+      have_norm = false;
       __syncthreads();
       continue;
     }
@@ -475,22 +488,48 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
     }
     if (tid == 0) { dd[j] = A[j * pa + j]; ee[j] = alpha; hv[int64_t(n) * n + j] = beta; }
     __syncthreads();
-    for (int i = tid; i < m; i += kThreads) {            // p = beta * A_t v
-      const double *row = A + (j + 1 + i) * pa + j + 1;
-      double acc = 0.0;
-      for (int k = 0; k < m; ++k) acc += row[k] * vv[k];
-      pp[i] = beta * acc;
+    double vp = 0.0;
+    for (int r = grp; r < m; r += kThreads / 4) {        // p = beta * A_t v
+      const double *row = A + (j + 1 + r) * pa + j + 1;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int k = sub;
+      for (; k + 12 < m; k += 16) {
+        a0 += row[k] * vv[k];
+        a1 += row[k + 4] * vv[k + 4];
+        a2 += row[k + 8] * vv[k + 8];
+        a3 += row[k + 12] * vv[k + 12];
+      }
+      for (; k < m; k += 4) a0 += row[k] * vv[k];
+      double acc = (a0 + a1) + (a2 + a3);
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (sub == 0) {
+        pp[r] = beta * acc;
+        vp += vv[r] * (beta * acc);
+      }
     }
+    vp = wave_sum(vp);
+    if (lane == 0) rs2[wave] = vp;
     __syncthreads();
-    part = 0.0;
-    for (int i = tid; i < m; i += kThreads) part += vv[i] * pp[i];
-    const double K = 0.5 * beta * block_sum(part, E.red);
-    for (int i = tid; i < m; i += kThreads) ww[i] = pp[i] - K * vv[i];
-    __syncthreads();
-    for (int e = tid; e < m * m; e += kThreads) {        // A_t -= v w^T + w v^T
-      const int a = e / m, b = e % m;
-      A[(j + 1 + a) * pa + j + 1 + b] -= vv[a] * ww[b] + ww[a] * vv[b];
+    const double K2 = beta * ((rs2[0] + rs2[1]) + (rs2[2] + rs2[3]));   // 2K
+    double nxt = 0.0;
+    for (int bh = 0; bh < m; bh += 64) {                 // A_t -= v p^T + p v^T - 2K v v^T
+      const int b = bh + lane;
+      if (b < m) {
+        const double vb = vv[b], pb = pp[b];
+#pragma unroll 4
+        for (int a = wave; a < m; a += kThreads / 64) {
+          const double va = vv[a];
+          double *x = A + (j + 1 + a) * pa + j + 1 + b;
+          const double val = *x - (va * pb + pp[a] * vb - K2 * va * vb);
+          *x = val;
+          if (b == 0 && a >= 1) nxt += val * val;        // next column, below its diagonal
+        }
+      }
     }
+    nxt = wave_sum(nxt);
+    if (lane == 0) rs[wave] = nxt;
+    have_norm = true;
     __syncthreads();
   }
   if (tid == 0) {
@@ -506,7 +545,6 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
 
   double *Z = A;
   for (int e = tid; e < n * n; e += kThreads) Z[e] = (e / n == e % n) ? 1.0 : 0.0;
-  const int lane = tid & 63;
   // Every wave that owns rows of Z (and wave 0, whose copy yields the eigenvalues)
   // runs the same chase on a private copy of (d, e) in LDS, so no barrier is needed
   // inside the iteration. Within a sweep step i reads d[i], e[i] and writes index
@@ -622,27 +660,54 @@ __device__ int keep_rank(const double *w, int navail, int n, int ucols, const Ke
   return k;
 }
 
-// z <- Q z for the k kept columns of Z (E.isrt[0..k)), last reflector first
+// z <- Q z for the k kept columns of Z (E.isrt[0..k)), last reflector first. Dot
+// products run 4 lanes per column with two partial sums per lane; the next
+// reflector is staged into the other buffer during the update, so each reflector
+// costs two barriers.
 __device__ void back_transform(const EigWs &E, int k) {
-  const int n = E.n, tid = threadIdx.x;
+  const int n = E.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, sub = tid & 3, grp = tid >> 2;
   double *Z = E.A;
-  for (int j = n - 3; j >= 0; --j) {
+  int cur = 0;
+  int j = n - 3;
+  if (j >= 0) {
+    for (int i = tid; i < n - j - 1; i += kThreads) E.vv[i] = E.hv[int64_t(j) * n + i];
+    __syncthreads();
+  }
+  for (; j >= 0; --j) {
     const int m = n - j - 1;
     const double beta = E.hv[int64_t(n) * n + j];
-    if (beta == 0.0) continue;
-    for (int i = tid; i < m; i += kThreads) E.vv[i] = E.hv[int64_t(j) * n + i];
-    __syncthreads();
-    for (int t = tid; t < k; t += kThreads) {
-      const double *z = Z + E.isrt[t] * n + j + 1;
-      double acc = 0.0;
-      for (int i = 0; i < m; ++i) acc += E.vv[i] * z[i];
-      E.pp[t] = beta * acc;
+    const double *v = cur ? E.ww : E.vv;
+    double *vnext = cur ? E.vv : E.ww;
+    if (beta != 0.0) {
+      for (int t = grp; t < k; t += kThreads / 4) {
+        const double *z = Z + E.isrt[t] * n + j + 1;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int i = sub;
+        for (; i + 12 < m; i += 16) {
+          a0 += v[i] * z[i];
+          a1 += v[i + 4] * z[i + 4];
+          a2 += v[i + 8] * z[i + 8];
+          a3 += v[i + 12] * z[i + 12];
+        }
+        for (; i < m; i += 4) a0 += v[i] * z[i];
+        double acc = (a0 + a1) + (a2 + a3);
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (sub == 0) E.pp[t] = beta * acc;
+      }
+      __syncthreads();
+      for (int ih = 0; ih < m; ih += 64) {
+        const int i = ih + lane;
+        if (i < m) {
+          const double vi = v[i];
+#pragma unroll 4
+          for (int t = wave; t < k; t += kThreads / 64) Z[E.isrt[t] * n + j + 1 + i] -= E.pp[t] * vi;
+        }
+      }
     }
-    __syncthreads();
-    for (int e = tid; e < m * k; e += kThreads) {
-      const int t = e / m, i = e % m;
-      Z[E.isrt[t] * n + j + 1 + i] -= E.pp[t] * E.vv[i];
-    }
+    if (j > 0)
+      for (int i = tid; i < m + 1; i += kThreads) vnext[i] = E.hv[int64_t(j - 1) * n + i];
+    cur ^= 1;
     __syncthreads();
   }
 }
