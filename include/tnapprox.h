@@ -62,8 +62,11 @@ typedef struct {
 
 typedef enum {
   TN_FP64 = 0,          /* every contraction in FP64 on the FP64 matrix cores */
-  TN_SPLIT_BF16X3 = 1,  /* contractions as 3 BF16 products of hi/lo splits, FP32 accumulate */
-  TN_SPLIT_FP16X3 = 2   /* the same with FP16 splits (lo part pre-scaled) */
+  TN_SPLIT_BF16X3 = 1,  /* contractions on the BF16 matrix cores: each operand scaled by a
+                           power of two to max |x| in [1/2, 1), split into three BF16 parts,
+                           the six part products of order <= 2 accumulated in FP32; the
+                           eigensolve, rescaling and log accumulation stay FP64 */
+  TN_SPLIT_FP16X3 = 2   /* the same with FP16 parts on the FP16 matrix cores */
 } tn_precision;
 
 typedef enum {
@@ -184,10 +187,12 @@ int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env
                   int64_t *stats);
 
 /* C (M x N, row-major) = A B with A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn],
- * through the contraction GEMM (FP64 matrix cores). lo_split sets the inner size of
- * the two-level row/column index maps. */
+ * through the contraction GEMM in the given tn_precision (FP64 matrix cores, or the
+ * split BF16 / FP16 products). lo_split sets the inner size of the two-level
+ * row/column index maps. */
 int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, int64_t sbk,
-                  int64_t sbn, double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split);
+                  int64_t sbn, double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split,
+                  int32_t precision);
 
 /* U (n x ucols, row-major) = the kept leading eigenvectors of (L + L^T)/2 (n x n),
  * zero columns past the kept rank, under opt's tau_rel and tau_deg (NULL: defaults).

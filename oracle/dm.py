@@ -52,6 +52,12 @@ TAU_REL = 1e-15
 TAU_DEG = 1e-12
 CLUSTER_FLOOR = 1e-10
 
+# The symmetric eigensolver keep() calls. Any backward-stable one gives an equally
+# valid result; swapping it (e.g. for LAPACK's relatively robust representation
+# driver) measures how far the method's result is fixed by FP64 arithmetic on a
+# given network.
+EIGH = np.linalg.eigh
+
 
 # ---------------------------------------------------------------- labelled tensors
 
@@ -155,7 +161,7 @@ def keep(L: np.ndarray, chi: int, tau_rel=TAU_REL, tau_deg=TAU_DEG):
     eigenvalues below both floors, so they never change k. If nothing survives,
     min(chi, dim) vectors are kept and fallback is True.
     """
-    w, v = np.linalg.eigh(L)
+    w, v = EIGH(L)
     w = w[::-1].copy()
     v = v[:, ::-1].copy()
     dim = len(w)

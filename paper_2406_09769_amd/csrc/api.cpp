@@ -266,13 +266,15 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int
     if (env_sizes[i] < 1) return fail(TN_EINVAL, "env_size must be >= 1");
   }
   tn_options o = opt ? *opt : defaults();
-  if (o.precision != TN_FP64) return fail(TN_EUNSUPPORTED, "precision form not available in this build");
+  if (o.precision != TN_FP64 && o.precision != TN_SPLIT_BF16X3 && o.precision != TN_SPLIT_FP16X3)
+    return fail(TN_EINVAL, "unknown precision");
   if (o.eig != TN_EIG_EXACT && o.eig != TN_EIG_LEARNED) return fail(TN_EINVAL, "unknown eigensolve mode");
   if (o.eig == TN_EIG_LEARNED && !o.model) return fail(TN_EINVAL, "learned eigensolve needs a model");
   if (o.eig == TN_EIG_LEARNED && !(o.residual_tol > 0)) return fail(TN_EINVAL, "residual_tol must be > 0");
   if (!(o.tau_rel >= 0) || !(o.tau_deg >= 0)) return fail(TN_EINVAL, "tau_rel and tau_deg must be >= 0");
   tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
   kp.residual_tol = o.residual_tol;
+  kp.split = int(o.precision);
   if (o.eig == TN_EIG_LEARNED) kp.model = o.model->d_w;
   return contract_batch(nets, paths, max_ranks, env_sizes, n, o, kp, outs);
 }
@@ -594,9 +596,10 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
 }
 
 int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, int64_t sbk, int64_t sbn,
-                  double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split) {
+                  double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split, int32_t precision) {
   g_err.clear();
   if (!A || !B || !C || M < 1 || N < 1 || K < 1) return fail(TN_EINVAL, "bad gemm arguments");
+  if (precision < TN_FP64 || precision > TN_SPLIT_FP16X3) return fail(TN_EINVAL, "unknown precision");
   if (lo_split < 1) lo_split = 1;
   std::vector<int32_t> tab;
   auto push_map = [&](int32_t n, int64_t stride, tn::IdxMap &m) {
@@ -631,6 +634,7 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
   op.c = 0;
   std::vector<double> ws(int64_t(M) * N, 0.0);
   tn::KeepParams kp{1e-15, 1e-12, tn::kClusterFloor};
+  kp.split = precision;
   int rc = run_single({op}, tab, ws, cst, kp, nullptr);
   if (rc != TN_OK) return rc;
   std::memcpy(C, ws.data(), ws.size() * 8);

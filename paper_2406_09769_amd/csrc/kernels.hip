@@ -269,14 +269,220 @@ __device__ void gemm_piped(const Op &op, const double *__restrict__ A, const dou
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- split-precision GEMM
+//
+// Precision form of a GEMM op: both operands are scaled by exact powers of two
+// (max |x| of the op's valid box brought into [1/2, 1)), every value is split into
+// three 16-bit floats, each the rounding of what the previous ones leave, and the
+// product is the sum of the six part products of order <= 2 (hh, hm, mh, hl, lh, mm)
+// on the 16-bit matrix cores with FP32 accumulation. BF16 (8-bit significand, FP32
+// range): x = h + m + l, one accumulator. FP16 (11-bit significand, narrow range):
+// the remainders are scaled up before rounding, x = h + 2^-11 m + 2^-22 l, so the
+// parts stay normal, and the products of each order get their own accumulator,
+// combined as acc0 + 2^-11 acc1 + 2^-22 acc2. The result is scaled back exactly and
+// stored in FP64.
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ double bf16_val(unsigned short b) { return double(__uint_as_float((unsigned int)b << 16)); }
+
+template <int SPLIT>
+__device__ __forceinline__ void split3(double x, unsigned short &h, unsigned short &m, unsigned short &l) {
+  if (SPLIT == 1) {
+    h = bf16_rne(float(x));
+    const double r1 = x - bf16_val(h);
+    m = bf16_rne(float(r1));
+    const double r2 = r1 - bf16_val(m);
+    l = bf16_rne(float(r2));
+  } else {
+    const _Float16 hh = _Float16(float(x));
+    const double r1 = (x - double(hh)) * 2048.0;             // exact
+    const _Float16 mm = _Float16(float(r1));
+    const double r2 = (r1 - double(mm)) * 2048.0;
+    const _Float16 ll = _Float16(float(r2));
+    h = __builtin_bit_cast(unsigned short, hh);
+    m = __builtin_bit_cast(unsigned short, mm);
+    l = __builtin_bit_cast(unsigned short, ll);
+  }
+}
+
+template <int SPLIT>
+__device__ __forceinline__ v4f mfma16(unsigned long long a, unsigned long long b, v4f c) {
+  if (SPLIT == 1)
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, a), __builtin_bit_cast(v4s, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, a), __builtin_bit_cast(v4h, b), c, 0, 0, 0);
+}
+
+// LDS of one stage: three planes of A (MB rows of KC + 4 parts, k fastest) and three
+// planes of B (NB columns of KC + 4 parts, k fastest), as 16-bit words.
+constexpr int split_stage_words(int MB, int NB, int KC) { return 3 * (MB + NB) * (KC + 4); }
+
+template <int MB, int NB, int KC, int TM, int TN, int SPLIT>
+__device__ void gemm_split(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
+                           double *__restrict__ C, double *lds, int M, int N, int K, const int32_t *kA,
+                           const int32_t *kB, const int32_t *rA, const int32_t *cB, const int32_t *rC,
+                           const int32_t *cC, double sa, double sb) {
+  constexpr int WN = NB / (16 * TN);
+  static_assert((MB / (16 * TM)) * WN == 4, "4 waves per block");
+  static_assert(KC % 16 == 0, "k chunk of whole 16-deep MFMA steps");
+  constexpr int P = KC + 4;                        // parts per row / column (8-byte aligned runs of 4)
+  constexpr int SW = split_stage_words(MB, NB, KC);
+  constexpr int LA = (MB * KC + kThreads - 1) / kThreads;
+  constexpr int LB = (KC * NB + kThreads - 1) / kThreads;
+  unsigned short *W16 = reinterpret_cast<unsigned short *>(lds);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const bool akf = (op.flags & F_A_KFAST) != 0;
+  const bool bnf = (op.flags & F_B_NFAST) != 0;
+  const int nbm = (M + MB - 1) / MB, nbn = (N + NB - 1) / NB, nch = (K + KC - 1) / KC;
+  const int steps = nbm * nbn * nch;
+  double ra[LA], rb[LB];
+  auto load = [&](int s) {
+    const int blk = s / nch, ch = s - blk * nch;
+    const int m0 = (blk / nbn) * MB, n0 = (blk % nbn) * NB, k0 = ch * KC;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + kThreads * q;
+      const int i = akf ? e / KC : e % MB, k = akf ? e % KC : e / MB;
+      double x = 0.0;
+      if (e < MB * KC && m0 + i < M && k0 + k < K) x = A[int64_t(rA[m0 + i]) + kA[k0 + k]];
+      ra[q] = x;
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + kThreads * q;
+      const int j = bnf ? e % NB : e / KC, k = bnf ? e / NB : e % KC;
+      double y = 0.0;
+      if (e < KC * NB && n0 + j < N && k0 + k < K) y = B[int64_t(cB[n0 + j]) + kB[k0 + k]];
+      rb[q] = y;
+    }
+  };
+  auto stash = [&](int buf) {
+    unsigned short *a3 = W16 + buf * SW, *b3 = a3 + 3 * MB * P;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + kThreads * q;
+      const int i = akf ? e / KC : e % MB, k = akf ? e % KC : e / MB;
+      if (e < MB * KC) {
+        unsigned short h, m, l;
+        split3<SPLIT>(ra[q] * sa, h, m, l);
+        a3[i * P + k] = h;
+        a3[(MB + i) * P + k] = m;
+        a3[(2 * MB + i) * P + k] = l;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + kThreads * q;
+      const int j = bnf ? e % NB : e / KC, k = bnf ? e / NB : e % KC;
+      if (e < KC * NB) {
+        unsigned short h, m, l;
+        split3<SPLIT>(rb[q] * sb, h, m, l);
+        b3[j * P + k] = h;
+        b3[(NB + j) * P + k] = m;
+        b3[(2 * NB + j) * P + k] = l;
+      }
+    }
+  };
+  const double unscale = 1.0 / (sa * sb);           // exact: a power of two
+  constexpr int NACC = SPLIT == 1 ? 1 : 3;          // FP16: one accumulator per order
+  v4f acc[NACC][TM][TN];
+#pragma unroll
+  for (int o = 0; o < NACC; ++o)
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) acc[o][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  constexpr int O1 = NACC > 1 ? 1 : 0, O2 = NACC > 1 ? 2 : 0;
+  if (steps > 0) load(0);
+  for (int s = 0; s < steps; ++s) {
+    const int buf = s & 1;
+    stash(buf);
+    __syncthreads();
+    if (s + 1 < steps) load(s + 1);
+    const int blk = s / nch, ch = s - blk * nch;
+    const unsigned short *a3 = W16 + buf * SW, *b3 = a3 + 3 * MB * P;
+    const int kq = 4 * (lane >> 4);                 // this lane's 4 k values of a 16-deep step
+    for (int kk = 0; kk < KC; kk += 16) {
+      unsigned long long ah[TM], am[TM], al[TM], bh[TN], bm[TN], bl[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        const int r = wm * TM * 16 + a * 16 + (lane & 15);
+        ah[a] = *reinterpret_cast<const unsigned long long *>(a3 + r * P + kk + kq);
+        am[a] = *reinterpret_cast<const unsigned long long *>(a3 + (MB + r) * P + kk + kq);
+        al[a] = *reinterpret_cast<const unsigned long long *>(a3 + (2 * MB + r) * P + kk + kq);
+      }
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int c = wn * TN * 16 + b * 16 + (lane & 15);
+        bh[b] = *reinterpret_cast<const unsigned long long *>(b3 + c * P + kk + kq);
+        bm[b] = *reinterpret_cast<const unsigned long long *>(b3 + (NB + c) * P + kk + kq);
+        bl[b] = *reinterpret_cast<const unsigned long long *>(b3 + (2 * NB + c) * P + kk + kq);
+      }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {               // small terms first
+          acc[O2][a][b] = mfma16<SPLIT>(am[a], bm[b], acc[O2][a][b]);
+          acc[O2][a][b] = mfma16<SPLIT>(al[a], bh[b], acc[O2][a][b]);
+          acc[O2][a][b] = mfma16<SPLIT>(ah[a], bl[b], acc[O2][a][b]);
+          acc[O1][a][b] = mfma16<SPLIT>(am[a], bh[b], acc[O1][a][b]);
+          acc[O1][a][b] = mfma16<SPLIT>(ah[a], bm[b], acc[O1][a][b]);
+          acc[0][a][b] = mfma16<SPLIT>(ah[a], bh[b], acc[0][a][b]);
+        }
+    }
+    if (ch == nch - 1) {
+      const int m0 = (blk / nbn) * MB, n0 = (blk % nbn) * NB;
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = m0 + wm * TM * 16 + a * 16 + 4 * (lane >> 4) + r;   // D: lane l, reg r = row 4(l/16) + r
+            const int col = n0 + wn * TN * 16 + b * 16 + (lane & 15);
+            double v = double(acc[0][a][b][r]);
+            if (NACC > 1) v += double(acc[O1][a][b][r]) * 0x1p-11 + double(acc[O2][a][b][r]) * 0x1p-22;
+            if (row < M && col < N) C[int64_t(rC[row]) + cC[col]] = v * unscale;
+          }
+#pragma unroll
+          for (int o = 0; o < NACC; ++o) acc[o][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ double block_max(double v, double *red);
+
+// 2^-e with e the frexp exponent of max |x| over a valid box (1 for an all-zero box)
+__device__ double pow2_scale(double amax) {
+  if (!(amax > 0.0)) return 1.0;
+  int e;
+  frexp(amax, &e);
+  return ldexp(1.0, -e);
+}
+
 // LDS doubles of the two stages of a gemm_piped configuration
 constexpr int piped_stage_doubles(int MB, int NB, int KC) { return 2 * (KC * (MB + 1) + KC * (NB + 1)); }
 constexpr int kPipedTiles = piped_stage_doubles(32, 128, 32);   // the largest configuration below
+static_assert(2 * split_stage_words(64, 64, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
+static_assert(2 * split_stage_words(32, 128, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
+static_assert(2 * split_stage_words(16, 256, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
 
 // One GEMM op. Returns false when its offsets do not fit the LDS cache (the caller
 // then runs gemm_tiles).
 __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
-                        double *__restrict__ C, const int32_t *__restrict__ tab, double *lds, NetScalars *sc) {
+                        double *__restrict__ C, const int32_t *__restrict__ tab, double *lds, NetScalars *sc,
+                        int split) {
   const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
   const int64_t NS = op.bn.n;
   if (2 * (int64_t(M) + N + K) > 2 * int64_t(kLdsDoubles - kPipedTiles)) return false;
@@ -300,6 +506,23 @@ __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double
     cC[n] = sn;
   }
   __syncthreads();
+  if (split) {
+    double am = 0.0, bm = 0.0;                   // per-tensor power-of-two scales
+    for (int e = tid; e < M * K; e += kThreads) am = fmax(am, fabs(A[int64_t(rA[e / K]) + kA[e % K]]));
+    for (int e = tid; e < K * N; e += kThreads) bm = fmax(bm, fabs(B[int64_t(cB[e / K]) + kB[e % K]]));
+    const double sa = pow2_scale(block_max(am, lds + kPipedTiles - 8));
+    const double sb = pow2_scale(block_max(bm, lds + kPipedTiles - 8));
+    if (split == 1) {
+      if (M <= 16) gemm_split<16, 256, 16, 1, 4, 1>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
+      else if (M <= 32) gemm_split<32, 128, 16, 2, 2, 1>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
+      else gemm_split<64, 64, 16, 2, 2, 1>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
+    } else {
+      if (M <= 16) gemm_split<16, 256, 16, 1, 4, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
+      else if (M <= 32) gemm_split<32, 128, 16, 2, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
+      else gemm_split<64, 64, 16, 2, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
+    }
+    return true;
+  }
   if (M <= 16)
     gemm_piped<16, 512, 8, 1, 8>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC);
   else if (M <= 32)
@@ -1086,7 +1309,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
       case OP_GEMM: {
         const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
         const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-        if (!gemm_op(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc))
+        if (!gemm_op(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc, kp.split))
           gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1, nd.sc);
         break;
       }

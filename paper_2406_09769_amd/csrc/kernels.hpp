@@ -28,6 +28,7 @@ struct KeepParams {
   float *hx, *hy;          // harvest: feature rows (8 floats) and leverage targets, or null
   int *hcount;             // harvest: rows written so far (atomic)
   long long hcap;          // harvest: capacity in rows
+  int split;               // contraction precision: 0 FP64, 1 BF16 x3 split, 2 FP16 x3 split
 };
 
 constexpr double kClusterFloor = 1e-10;

@@ -4,6 +4,8 @@ Calls only oracle/ (and the seeded input generators). Usage:
     python tests/golden/make_golden.py w2   # 64x64 2D Ising, 8 betas x chi {32,64} x env {1,2}
     python tests/golden/make_golden.py w4   # 64 signed-J random 3-regular graphs, beta 1, chi 64
     python tests/golden/make_golden.py w5   # 32 random 3-SAT #CSP formulas, n 150, m 450, chi 32
+    python tests/golden/make_golden.py w4spread  # how far FP64 fixes each W4 result (see spread())
+    python tests/golden/make_golden.py w5small   # 8 random 3-SAT formulas, n 50, m 150, chi 32
 """
 import json
 import math
@@ -37,9 +39,51 @@ def w2(out_path):
                "rows": rows}, open(out_path, "w"), indent=1)
 
 
+def _spread_one(i):
+    """Oracle result of W4 instance i under three other equally valid FP64 evaluations:
+    LAPACK's MRRR driver (evr) in place of the default divide-and-conquer one, and the
+    default solver on the network with every tensor entry scaled by (1 + 1e-15 z),
+    z standard normal (two seeds). Returns the largest |dlnZ|/N from the stored value."""
+    import copy
+    import numpy as np
+    import scipy.linalg as sl
+    gold = json.load(open(os.path.join(HERE, "w4_oracle.json")))["rows"][i]
+    net = inputs.rrg_batch(i + 1)[i]
+    assert net.name == gold["name"]
+    vals = {}
+    dm.EIGH = lambda L: sl.eigh(L, driver="evr")
+    try:
+        vals["evr"] = dm.contract_approx(net, 64, 1)[0]
+    finally:
+        dm.EIGH = np.linalg.eigh
+    for seed in (0, 1):
+        rng = np.random.default_rng(seed)
+        net2 = copy.deepcopy(net)
+        net2.tensors = [t * (1.0 + 1e-15 * rng.standard_normal(t.shape)) for t in net.tensors]
+        vals[f"perturbed_{seed}"] = dm.contract_approx(net2, 64, 1)[0]
+    dev = {k: abs(v - gold["log_abs"]) / net.n_sites for k, v in vals.items()}
+    row = {"index": i, "name": net.name, "spread": max(dev.values()), **dev}
+    print(json.dumps(row), flush=True)
+    return row
+
+
+def spread(out_path, workers=4):
+    with Pool(workers) as pool:
+        rows = sorted(pool.map(_spread_one, range(64)), key=lambda r: r["index"])
+    json.dump({"workload": "the 64 graphs of w4_oracle.json",
+               "what": "largest |dlnZ|/N between the stored oracle value and the oracle under an "
+                       "alternative LAPACK eigensolver (evr) or 1e-15 relative input noise (2 seeds)",
+               "rows": rows}, open(out_path, "w"), indent=1)
+
+
 def _one(args):
     kind, i, chi = args
-    net = inputs.rrg_batch(i + 1)[i] if kind == "w4" else inputs.csp_batch(i + 1)[i]
+    if kind == "w4":
+        net = inputs.rrg_batch(i + 1)[i]
+    elif kind == "w5":
+        net = inputs.csp_batch(i + 1)[i]
+    else:
+        net = inputs.csp_batch(i + 1, n_vars=50)[i]
     t = time.time()
     st = dm.Stats()
     v, s = dm.contract_approx(net, chi, 1, stats=st)
@@ -55,7 +99,9 @@ def batch(kind, count, chi, out_path, workers=4):
     desc = {"w4": ("64 signed-J random 3-regular graphs, n_i = 2*U{50..150}, J ~ N(0,1), beta 1, "
                    "seed 4000+i, greedy path", "paper_2406_09769_amd.inputs.rrg_batch(64)"),
             "w5": ("32 random 3-SAT #CSP formulas, n 150, m 450, seed 5000+i, greedy path",
-                   "paper_2406_09769_amd.inputs.csp_batch(32)")}[kind]
+                   "paper_2406_09769_amd.inputs.csp_batch(32)"),
+            "w5small": ("8 random 3-SAT #CSP formulas, n 50, m 150, seed 5000+i, greedy path",
+                        "paper_2406_09769_amd.inputs.csp_batch(8, n_vars=50)")}[kind]
     json.dump({"workload": desc[0], "generator": desc[1],
                "oracle": f"oracle.dm.contract_approx(net, {chi}, 1) with default cutoffs",
                "rows": rows}, open(out_path, "w"), indent=1)
@@ -69,3 +115,7 @@ if __name__ == "__main__":
         batch("w4", 64, 64, os.path.join(HERE, "w4_oracle.json"))
     elif which == "w5":
         batch("w5", 32, 32, os.path.join(HERE, "w5_oracle.json"))
+    elif which == "w4spread":
+        spread(os.path.join(HERE, "w4_spread.json"))
+    elif which == "w5small":
+        batch("w5small", 8, 32, os.path.join(HERE, "w5_small_oracle.json"))

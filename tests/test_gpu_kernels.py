@@ -97,3 +97,24 @@ def test_rescale_is_exact_power_of_two(T, scale):
     _, want = np.frexp(np.max(np.abs(x)))
     assert e == want
     assert np.array_equal(y, np.ldexp(x, -e))
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("M,N,K", [(5, 300, 37), (30, 130, 70), (90, 77, 51), (16, 512, 4), (64, 64, 16)])
+def test_gemm_split_precision_within_its_bound(T, precision, M, N, K):
+    """Split BF16 / FP16 products against the FP64 product. Bound, element by element:
+    |C - AB| <= 2^-20 (|A||B|): each value is carried to ~2^-24 relative by its three
+    parts, the dropped part products are below 2^-24 |a||b|, and the FP32 sums of the
+    six products over K add a few 2^-24 of the running sum; operands are scaled to a
+    common power of two first, so the bound holds at any magnitude."""
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.standard_normal((M, K)) * np.exp(rng.uniform(-3, 0, (M, K)))
+    B = rng.standard_normal((K, N)) * np.exp(rng.uniform(-3, 0, (K, N)))
+    for scale in (1.0, 2.0 ** 40, 2.0 ** -37):
+        C = T.tn_debug_gemm(A * scale, B, precision=precision)
+        ref = (A * scale) @ B
+        bound = 2.0 ** -20 * (np.abs(A * scale) @ np.abs(B))
+        assert np.all(np.abs(C - ref) <= bound + 1e-300), (precision, scale, np.max(np.abs(C - ref) / bound))
+        # and it is not exact FP64 arithmetic in disguise: the error is at the split level
+        if precision == 1 and scale == 1.0 and K >= 16:
+            assert np.max(np.abs(C - ref)) > 0

@@ -1,0 +1,73 @@
+"""The precision form (split BF16 x3 / FP16 x3 contractions, FP64 eigensolve) against
+the FP64 oracle.
+
+Stated per-result bound: |ln|Z|_form - ln|Z|_oracle| / N <= 1e-6. Each contraction of
+the form carries a relative error of at most 2^-20 of |A||B| (tested element by
+element in test_gpu_kernels.py); a step of the method normalises a product of a few
+such contractions, so its logarithm moves by O(2^-20) at most, and a network of N
+sites takes about N steps. Every error is printed; the measured worst case on the
+64x64 workload is two orders of magnitude inside the bound.
+"""
+import json
+import os
+
+import pytest
+
+from paper_2406_09769_amd import inputs
+from oracle import dm
+
+pytestmark = pytest.mark.gpu
+BOUND = 1e-6
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2406_09769_amd import tnapprox
+    return tnapprox
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("net_fn,chi,env", [
+    (lambda: inputs.ising_2d(6, 6, 0.44), 4, 1),
+    (lambda: inputs.ising_2d(6, 6, 0.44), 16, 1),
+    (lambda: inputs.ising_2d(16, 16, 0.44), 16, 2),
+    (lambda: inputs.ising_3d(4, 4, 4, 0.2217), 8, 1),
+    (lambda: inputs.ising_rrg(40, 1.0, 4100), 16, 1),
+])
+def test_precision_form_within_bound(T, precision, net_fn, chi, env):
+    net = net_fn()
+    h = T.create_network(net)
+    r = T.tn_contract_approx(h, net.slices, chi, env, precision=precision)
+    v, s = dm.contract_approx(net, chi, env)
+    d = abs(r.log_abs - v) / net.n_sites
+    print(f"{net.name} chi={chi} env={env} precision={precision}: |dlnZ|/N {d:.3e}", flush=True)
+    assert r.sign == s and d <= BOUND
+
+
+def test_fp64_unchanged_by_the_option(T):
+    net = inputs.ising_2d(12, 12, 0.44)
+    h = T.create_network(net)
+    a = T.tn_contract_approx(h, net.slices, 16, 1)
+    b = T.tn_contract_approx(h, net.slices, 16, 1, precision=T.TN_FP64)
+    assert a.log_abs == b.log_abs
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_w2_full_size_precision_form(T, precision):
+    """All 32 networks of the 64x64 workload in one launch."""
+    gold = json.load(open(os.path.join(HERE, "golden", "w2_oracle.json")))["rows"]
+    nets, chis, envs, gl = [], [], [], []
+    for chi, env in ((32, 1), (32, 2), (64, 1), (64, 2)):
+        for b in inputs.w2_betas():
+            nets.append(inputs.ising_2d(64, 64, b))
+            chis.append(chi)
+            envs.append(env)
+            gl.append(next(x for x in gold if x["chi"] == chi and x["env"] == env and abs(x["beta"] - b) < 1e-12))
+    hs = [T.create_network(n) for n in nets]
+    rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], chis, envs, precision=precision)
+    errs = [abs(r.log_abs - g["log_abs"]) / 4096 for r, g in zip(rs, gl)]
+    print(f"64x64 workload, precision={precision}: kernel {rs[0].seconds:.3f} s, worst |dlnZ|/N {max(errs):.3e}, "
+          f"per (chi, env) group {[f'{max(errs[8 * i:8 * i + 8]):.1e}' for i in range(4)]}", flush=True)
+    assert all(r.sign == g["sign"] for r, g in zip(rs, gl))
+    assert max(errs) <= BOUND
