@@ -6,10 +6,13 @@ temperatures linspace(0.30, 0.60, 8), each at max_rank chi in {32, 64} and
 env_size in {1, 2}: 32 networks, contracted in ONE persistent launch (one
 workgroup per network). Inputs are uploaded once before timing (tn_create).
 
-Prints one JSON line: networks/s over the timed steps, the roofline of the
-interpreter kernel (algorithmic GEMM flops per launch over its HIP-event
-duration), the per-site error of every result against the stored oracle values,
-and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: networks/s over the timed steps (plain FP64 method), the
+roofline of the interpreter kernel (algorithmic GEMM flops per launch over its
+HIP-event duration), the per-site error of every result against the stored oracle
+values, the same workload once in each other form (split BF16x3 / FP16x3
+contractions; learned warm start of the eigensolve with an MLP trained on the GPU
+beforehand) with its networks/s and worst error, and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -51,6 +54,18 @@ def golden_errors(results, chis, envs):
         g = next(x for x in gold if x["chi"] == chi and x["env"] == env and abs(x["beta"] - b) < 1e-12)
         errs.append(abs(r.log_abs - g["log_abs"]) / 4096 if r.sign == g["sign"] else float("inf"))
     return errs
+
+
+def train_model(T):
+    """The warm-start MLP trained on rows the method harvests from small lattices."""
+    from paper_2406_09769_amd import inputs
+    ds = T.Dataset(400_000)
+    for (L, b, chi) in ((16, 0.35, 16), (16, 0.44, 16), (16, 0.5, 16), (20, 0.44, 24)):
+        net = inputs.ising_2d(L, L, b)
+        T.tn_harvest(T.create_network(net), net.slices, chi, 1, ds)
+    m = T.Model(seed=7)
+    m.train(ds, steps=3000, batch=128, lr=3e-3, seed=11)
+    return m
 
 
 def cpu_baseline(sample: int):
@@ -129,6 +144,24 @@ def main():
     achieved = flops / ksec / 1e12
     errs = golden_errors(rs, chis, envs)
 
+    forms = {}
+    for name, kw in (("split_bf16x3", dict(precision=T.TN_SPLIT_BF16X3)),
+                     ("split_fp16x3", dict(precision=T.TN_SPLIT_FP16X3)),
+                     ("learned_warm_start", dict(eig=T.TN_EIG_LEARNED, model=train_model(T)))):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rf = T.tn_contract_approx_batch(handles, slices, chis, envs, stream=stream, **kw)
+        torch.cuda.synchronize()
+        dtf = time.perf_counter() - t1
+        ef = golden_errors(rf, chis, envs)
+        forms[name] = {"networks_per_s": round(len(nets) / dtf, 4), "kernel_ms": round(rf[0].seconds * 1e3, 3),
+                       "max_dlnZ_per_site_vs_oracle": (max(ef) if ef else None),
+                       "within_1e-8": (sum(e <= 1e-8 for e in ef) if ef else None)}
+        if name.startswith("learned"):
+            forms[name]["warm_starts_accepted"] = sum(r.n_learned for r in rf)
+            forms[name]["eigensolves"] = sum(r.n_eig for r in rf)
+        print(f"[bench] form {name}: {json.dumps(forms[name])}", file=sys.stderr, flush=True)
+
     line = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -151,6 +184,7 @@ def main():
                      "gemm_flops_per_launch": flops, "eig_flops_per_launch": eig_flops},
         "accuracy": {"max_dlnZ_per_site_vs_oracle": (max(errs) if errs else None),
                      "within_1e-8": (sum(e <= 1e-8 for e in errs) if errs else None)},
+        "forms": forms,
     }
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample)

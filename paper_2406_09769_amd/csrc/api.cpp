@@ -29,8 +29,17 @@ int fail(int code, const std::string &msg) {
     if (e_ != hipSuccess) return fail(TN_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// A run of ops executed one way: kind 0 = ops [first, last) by one workgroup,
+// 1 = GEMM op `first` over `blocks` workgroups, 2 = RESCALE op `first` likewise.
+struct Seg {
+  int kind;
+  int64_t first, last;
+  int blocks;
+};
+
 struct DevPlan {
   tn::Plan plan;
+  std::vector<Seg> segs;     // empty: the whole network fits one workgroup's pass
   tn::Op *d_ops = nullptr;
   int32_t *d_tab = nullptr;
   ~DevPlan() {
@@ -104,6 +113,48 @@ struct tn_dataset_s {
 
 namespace {
 
+int64_t box_static(const tn::Box &b) {
+  int64_t n = b.rest;
+  for (int d = 0; d < b.nd; ++d) n *= b.cap[d];
+  return n;
+}
+
+// Ops whose output exceeds 2^21 elements (or a GEMM above 2^32 flops) run over the
+// whole chip; the rest of such a network runs in single-workgroup stretches between
+// them. Networks without such ops keep the one-pass interpreter.
+void make_segments(DevPlan &dp) {
+  constexpr int64_t kBigOut = int64_t(1) << 21, kBigFlops = int64_t(1) << 32;
+  std::vector<Seg> segs;
+  bool any = false;
+  const auto &ops = dp.plan.ops;
+  for (int64_t i = 0; i < int64_t(ops.size()); ++i) {
+    const tn::Op &op = ops[size_t(i)];
+    int kind = 0, blocks = 0;
+    if (op.kind == tn::OP_GEMM) {
+      const int64_t M = op.am.n, N = op.bn.n, out = M * N;
+      if (out >= kBigOut || 2 * out * op.K >= kBigFlops) {
+        kind = 1;
+        blocks = int(std::min<int64_t>(tn::kGridBlocks, ((M + 63) / 64) * ((N + 63) / 64)));
+      }
+    } else if (op.kind == tn::OP_RESCALE) {
+      const int64_t out = box_static(op.bm) * box_static(op.bnb);
+      if (out >= kBigOut) {
+        kind = 2;
+        blocks = int(std::min<int64_t>(tn::kGridBlocks, (out + 2047) / 2048));
+      }
+    }
+    if (kind) {
+      any = true;
+      segs.push_back(Seg{kind, i, i + 1, std::max(blocks, 1)});
+    } else if (!segs.empty() && segs.back().kind == 0) {
+      segs.back().last = i + 1;
+    } else {
+      segs.push_back(Seg{0, i, i + 1, 1});
+    }
+  }
+  if (any) dp.segs = std::move(segs);
+}
+
 int get_plan(tn_net net, const std::vector<std::vector<int32_t>> &slices, int32_t chi, int32_t env,
              DevPlan **out) {
   PlanKey key{slices, chi, env};
@@ -117,6 +168,7 @@ int get_plan(tn_net net, const std::vector<std::vector<int32_t>> &slices, int32_
   bool unsup = false;
   std::string err = tn::make_plan(net->g, pa, dp->plan, &unsup);
   if (!err.empty()) return fail(unsup ? TN_EUNSUPPORTED : TN_EINVAL, err);
+  make_segments(*dp);
   size_t ob = dp->plan.ops.size() * sizeof(tn::Op), tb = std::max<size_t>(1, dp->plan.tables.size()) * 4;
   if (hipMalloc(&dp->d_ops, std::max<size_t>(ob, 64)) != hipSuccess ||
       hipMalloc(&dp->d_tab, tb) != hipSuccess)
@@ -153,33 +205,53 @@ tn_options defaults() {
   return o;
 }
 
-// Run a list of prepared networks in one interpreter launch.
+// Run a list of prepared networks: those that fit one workgroup's pass in one
+// persistent interpreter launch (one workgroup each), then each larger network op
+// run by op run on the same stream.
 int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &plans, const tn_options &o,
               const tn::KeepParams &kp, double *seconds, std::vector<tn::NetScalars> &sc_out) {
   hipStream_t st = reinterpret_cast<hipStream_t>(o.hip_stream);
   const size_t n = nets.size();
+  std::vector<size_t> order;                 // persistent ones first
+  for (size_t i = 0; i < n; ++i)
+    if (plans[i]->segs.empty()) order.push_back(i);
+  const size_t n_persist = order.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!plans[i]->segs.empty()) order.push_back(i);
   std::vector<tn::NetDev> nd(n);
   tn::NetScalars init{};
   init.sign = 1;
-  for (size_t i = 0; i < n; ++i) {
+  for (size_t q = 0; q < n; ++q) {
+    const size_t i = order[q];
     HIP_TRY(hipMemcpyAsync(nets[i]->d_sc, &init, sizeof(init), hipMemcpyHostToDevice, st));
-    nd[i].ops = plans[i]->d_ops;
-    nd[i].n_ops = int64_t(plans[i]->plan.ops.size());
-    nd[i].tab = plans[i]->d_tab;
-    nd[i].ws = nets[i]->d_ws;
-    nd[i].cst = nets[i]->d_const;
-    nd[i].sc = nets[i]->d_sc;
-    nd[i].dyn = reinterpret_cast<int32_t *>(nets[i]->d_ws + plans[i]->plan.dyn_off);
+    nd[q].ops = plans[i]->d_ops;
+    nd[q].n_ops = int64_t(plans[i]->plan.ops.size());
+    nd[q].tab = plans[i]->d_tab;
+    nd[q].ws = nets[i]->d_ws;
+    nd[q].cst = nets[i]->d_const;
+    nd[q].sc = nets[i]->d_sc;
+    nd[q].dyn = reinterpret_cast<int32_t *>(nets[i]->d_ws + plans[i]->plan.dyn_off);
   }
   tn::NetDev *d_nd = nullptr;
   if (hipMalloc(&d_nd, n * sizeof(tn::NetDev)) != hipSuccess) return fail(TN_ENOMEM, "launch descriptor allocation failed");
   std::unique_ptr<tn::NetDev, void (*)(tn::NetDev *)> guard(d_nd, [](tn::NetDev *p) { (void)hipFree(p); });
+  double *d_part = nullptr;
+  if (n_persist < n && hipMalloc(&d_part, tn::kGridBlocks * sizeof(double)) != hipSuccess)
+    return fail(TN_ENOMEM, "grid scratch allocation failed");
+  std::unique_ptr<double, void (*)(double *)> guard2(d_part, [](double *p) { if (p) (void)hipFree(p); });
   HIP_TRY(hipMemcpyAsync(d_nd, nd.data(), n * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, st));
-  HIP_TRY(tn::launch_interp(d_nd, int(n), kp, st));
+  if (n_persist > 0) HIP_TRY(tn::launch_interp(d_nd, int(n_persist), kp, st));
+  for (size_t q = n_persist; q < n; ++q) {
+    for (const Seg &sg : plans[order[q]]->segs) {
+      if (sg.kind == 0) HIP_TRY(tn::launch_interp_range(d_nd + q, sg.first, sg.last, kp, st));
+      else if (sg.kind == 1) HIP_TRY(tn::launch_gemm_grid(d_nd + q, sg.first, sg.blocks, st));
+      else HIP_TRY(tn::launch_rescale_grid(d_nd + q, sg.first, sg.blocks, d_part, st));
+    }
+  }
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -526,6 +598,9 @@ int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env
   stats[4] = dp->plan.eig_flops;
   stats[5] = dp->plan.n_eig;
   stats[6] = dp->plan.max_eig_dim;
+  int64_t grid_ops = 0;
+  for (const Seg &sg : dp->segs) grid_ops += sg.kind != 0 ? 1 : 0;
+  stats[7] = grid_ops;
   return TN_OK;
 }
 

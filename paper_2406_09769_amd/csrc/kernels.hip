@@ -1286,22 +1286,32 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
 
 // ---------------------------------------------------------------- interpreter
 
-__global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restrict__ nets, KeepParams kp) {
+// Stage op i of a network in LDS with every Box's slot ids replaced by the runtime
+// extents they hold (the whole workgroup takes part).
+__device__ void stage_op(const NetDev &nd, int64_t i, Op &s_op) {
+  const int tid = threadIdx.x;
+  constexpr int kOpWords = int(sizeof(Op) / 4);
+  static_assert(kOpWords <= kThreads, "Op must be staged by one pass of the workgroup");
+  if (tid < kOpWords) reinterpret_cast<int32_t *>(&s_op)[tid] = reinterpret_cast<const int32_t *>(nd.ops + i)[tid];
+  __syncthreads();
+  if (tid < 3 * kMaxDyn) {
+    Box *bx = tid < kMaxDyn ? &s_op.bm : (tid < 2 * kMaxDyn ? &s_op.bnb : &s_op.bk_);
+    const int d = tid % kMaxDyn;
+    if (d < bx->nd) bx->id[d] = nd.dyn[bx->id[d]];
+  }
+  __syncthreads();
+}
+
+// One workgroup walks ops [first, last) of its network (last < 0: to the end).
+__global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restrict__ nets, KeepParams kp,
+                                                          int64_t first, int64_t last) {
   __shared__ double lds[kLdsDoubles];
   __shared__ Op s_op;                 // the current op, Box slot ids replaced by extents
   const NetDev nd = nets[blockIdx.x];
   const int tid = threadIdx.x;
-  constexpr int kOpWords = int(sizeof(Op) / 4);
-  static_assert(kOpWords <= kThreads, "Op must be staged by one pass of the workgroup");
-  for (int64_t i = 0; i < nd.n_ops; ++i) {
-    if (tid < kOpWords) reinterpret_cast<int32_t *>(&s_op)[tid] = reinterpret_cast<const int32_t *>(nd.ops + i)[tid];
-    __syncthreads();
-    if (tid < 3 * kMaxDyn) {
-      Box *bx = tid < kMaxDyn ? &s_op.bm : (tid < 2 * kMaxDyn ? &s_op.bnb : &s_op.bk_);
-      const int d = tid % kMaxDyn;
-      if (d < bx->nd) bx->id[d] = nd.dyn[bx->id[d]];
-    }
-    __syncthreads();
+  const int64_t end = last < 0 ? nd.n_ops : last;
+  for (int64_t i = first; i < end; ++i) {
+    stage_op(nd, i, s_op);
     const Op &op = s_op;
     const int kind = op.kind;
     const long long t0 = wall_clock64();
@@ -1333,8 +1343,97 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
   }
 }
 
+// ---------------------------------------------------------------- grid-wide ops
+//
+// An op too large for one workgroup (a 3D environment holds up to 10^8 elements) runs
+// over the whole chip: every workgroup stages the op, then takes output tiles or
+// elements in a stride of the grid.
+
+constexpr int kGridLds = 2 * kTK * kPitch + kKCache;   // gemm_tiles: two k-slices and both k caches
+
+__global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__restrict__ ndp, int64_t i) {
+  __shared__ double lds[kGridLds];
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
+  const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
+  gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
+}
+
+// max |x| over this workgroup's share of the valid box -> partial[blockIdx.x]
+__global__ __launch_bounds__(kThreads) void rescale_max_kernel(const NetDev *__restrict__ ndp, int64_t i,
+                                                               double *partial) {
+  __shared__ double red[8];
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  const double *x = nd.ws + op.c;
+  const int32_t Cn = box_eff(op.bnb);
+  const int64_t total = int64_t(box_eff(op.bm)) * Cn, ncols = op.count;
+  double m = 0.0;
+  for (int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x; e < total; e += int64_t(gridDim.x) * kThreads) {
+    const int32_t r = int32_t(e / Cn), c = int32_t(e - int64_t(r) * Cn);
+    m = fmax(m, fabs(x[int64_t(box_conv(op.bm, r)) * ncols + box_conv(op.bnb, c)]));
+  }
+  m = block_max(m, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+// x *= 2^-e with e the frexp exponent of the max over all partials; the exponent is
+// added to the log accumulator once (F_ACCUM), a zero max marks Z = 0.
+__global__ __launch_bounds__(kThreads) void rescale_apply_kernel(const NetDev *__restrict__ ndp, int64_t i,
+                                                                 const double *partial, int nparts) {
+  __shared__ double red[8];
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  double m = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += kThreads) m = fmax(m, partial[q]);
+  m = block_max(m, red);
+  const bool accum = (op.flags & F_ACCUM) != 0;
+  if (!(m > 0.0) || !isfinite(m)) {
+    if (m == 0.0 && accum && blockIdx.x == 0 && threadIdx.x == 0) nd.sc->zero = 1;
+    return;
+  }
+  int ex;
+  frexp(m, &ex);
+  double *x = nd.ws + op.c;
+  const int32_t Cn = box_eff(op.bnb);
+  const int64_t total = int64_t(box_eff(op.bm)) * Cn, ncols = op.count;
+  for (int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x; e < total; e += int64_t(gridDim.x) * kThreads) {
+    const int32_t r = int32_t(e / Cn), c = int32_t(e - int64_t(r) * Cn);
+    const int64_t o = int64_t(box_conv(op.bm, r)) * ncols + box_conv(op.bnb, c);
+    x[o] = ldexp(x[o], -ex);
+  }
+  if (accum && blockIdx.x == 0 && threadIdx.x == 0) nd.sc->exp_sum += ex;
+}
+
 hipError_t launch_interp(const NetDev *nets_dev, int n_nets, const KeepParams &kp, hipStream_t stream) {
-  hipLaunchKernelGGL(interp_kernel, dim3(n_nets), dim3(kThreads), 0, stream, nets_dev, kp);
+  hipLaunchKernelGGL(interp_kernel, dim3(n_nets), dim3(kThreads), 0, stream, nets_dev, kp, int64_t(0), int64_t(-1));
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last, const KeepParams &kp,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(interp_kernel, dim3(1), dim3(kThreads), 0, stream, nd_dev, kp, first, last);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, hipStream_t stream) {
+  hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, double *partial, hipStream_t stream) {
+  hipLaunchKernelGGL(rescale_max_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rescale_apply_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i,
+                     (const double *)partial, blocks);
   return hipGetLastError();
 }
 

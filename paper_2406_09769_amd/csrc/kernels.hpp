@@ -41,4 +41,13 @@ hipError_t launch_mlp_train(float *w, float *m, float *v, const float *X, const 
 
 hipError_t launch_interp(const NetDev *nets_dev, int n_nets, const KeepParams &kp, hipStream_t stream);
 
+// Large networks, op by op: one workgroup over ops [first, last) of nd_dev's network;
+// one GEMM op or one RESCALE op over `blocks` workgroups (partial: blocks doubles of
+// device scratch).
+constexpr int kGridBlocks = 2048;
+hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last, const KeepParams &kp,
+                               hipStream_t stream);
+hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, hipStream_t stream);
+hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, double *partial, hipStream_t stream);
+
 }  // namespace tn

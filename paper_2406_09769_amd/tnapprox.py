@@ -234,9 +234,9 @@ def tn_plan_json(tensors_or_shapes, edges, slices, env_size: int) -> dict:
 
 def tn_plan_stats(h: Handle, slices, max_rank: int, env_size: int) -> dict:
     p = _PathArgs(slices)
-    st = (C.c_int64 * 7)()
+    st = (C.c_int64 * 8)()
     _check(LIB.tn_plan_stats(h.ptr, C.byref(p.path), int(max_rank), int(env_size), st))
-    keys = ["ops", "table_entries", "ws_doubles", "flops", "eig_flops", "n_eig", "max_eig_dim"]
+    keys = ["ops", "table_entries", "ws_doubles", "flops", "eig_flops", "n_eig", "max_eig_dim", "grid_ops"]
     return dict(zip(keys, list(st)))
 
 

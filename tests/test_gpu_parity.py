@@ -56,6 +56,17 @@ def test_narrow_strip_exact_at_chi64(T):
     assert abs(r.log_abs - exact.tm_2d(64, 12, 0.44)) / net.n_sites <= 1e-11
 
 
+@pytest.mark.parametrize("side,chi", [(5, 16), (6, 8)])
+def test_3d_with_chip_wide_ops(T, side, chi):
+    """Plane-by-plane 3D lattices whose largest environments exceed 2^21 elements: those
+    contractions and rescalings run over the whole chip, the rest in one workgroup."""
+    net = inputs.ising_3d(side, side, side, 0.2217)
+    h = T.create_network(net)
+    st = T.tn_plan_stats(h, net.slices, chi, 1)
+    assert st["grid_ops"] > 0
+    check(T, net, chi, 1)
+
+
 def test_3d_small(T):
     check(T, inputs.ising_3d(3, 3, 3, 0.25), 8, 1)
     net = inputs.ising_3d(4, 3, 3, 0.2217)
