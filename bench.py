@@ -29,6 +29,11 @@ METRIC = "networks/s + MFMA util at |dlnZ|/N<=1e-8: mixed+batched+learned vs pla
 PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 GROUPS = [(32, 1), (32, 2), (64, 1), (64, 2)]
+CUS = 256
+# HBM bytes per launch of interp_kernel on this workload: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+# (factors from a 256 MiB copy), from profiles/interp_kernel_w2_64x64_fp64_hbm.txt. Set to
+# None whenever the kernel changes until the counters are taken again.
+TRAFFIC_BYTES = 7.1335e9
 
 
 def workload():
@@ -98,7 +103,20 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=8, help="networks timed in the CPU oracle (0 = skip)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the runs of the other forms")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a buffer of MIB MiB once on the GPU (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe > 0:
+        import torch
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the workload's networks "
               "are independent and would be split across GPUs, which this build does not do.", file=sys.stderr)
@@ -136,7 +154,8 @@ def main():
 
     prof = {}
     for name, i in (("beta0.44_chi64_env1", 8 * 2 + 3), ("beta0.44_chi32_env1", 3)):
-        prof[name] = {k: round(v, 4) for k, v in T.tn_profile_last(handles[i]).items()}
+        prof[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in T.tn_profile_last(handles[i]).items()
+                      if not k.startswith("learned")}
     print(f"[bench] per-op device seconds of one network: {json.dumps(prof)}", file=sys.stderr, flush=True)
     flops = sum(r.flops for r in rs)
     eig_flops = sum(r.eig_flops for r in rs)
@@ -145,9 +164,12 @@ def main():
     errs = golden_errors(rs, chis, envs)
 
     forms = {}
-    for name, kw in (("split_bf16x3", dict(precision=T.TN_SPLIT_BF16X3)),
-                     ("split_fp16x3", dict(precision=T.TN_SPLIT_FP16X3)),
-                     ("learned_warm_start", dict(eig=T.TN_EIG_LEARNED, model=train_model(T)))):
+    form_list = [] if args.no_forms else [
+        ("split_bf16x3", lambda: dict(precision=T.TN_SPLIT_BF16X3)),
+        ("split_fp16x3", lambda: dict(precision=T.TN_SPLIT_FP16X3)),
+        ("learned_warm_start", lambda: dict(eig=T.TN_EIG_LEARNED, model=train_model(T)))]
+    for name, make_kw in form_list:
+        kw = make_kw()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         rf = T.tn_contract_approx_batch(handles, slices, chis, envs, stream=stream, **kw)
@@ -179,7 +201,8 @@ def main():
         "config": {"workload": "ising2d_64x64_open_J1_h0 x 8 betas linspace(0.30,0.60,8) x chi{32,64} x env{1,2}",
                    "networks": len(nets), "lattice": "64x64", "chi": [32, 64], "env_size": [1, 2]},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 5), "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 7), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 7), "traffic": TRAFFIC_BYTES,
+                     "workgroups": len(nets), "frac_of_cus_in_use": round(achieved / (PEAK_FP64_TFLOPS * len(nets) / CUS), 6),
                      "kernel": "interp_kernel", "kernel_ms": round(ksec * 1e3, 3),
                      "gemm_flops_per_launch": flops, "eig_flops_per_launch": eig_flops},
         "accuracy": {"max_dlnZ_per_site_vs_oracle": (max(errs) if errs else None),
