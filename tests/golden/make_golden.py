@@ -6,6 +6,7 @@ Calls only oracle/ (and the seeded input generators). Usage:
     python tests/golden/make_golden.py w5   # 32 random 3-SAT #CSP formulas, n 150, m 450, chi 32
     python tests/golden/make_golden.py w4spread  # how far FP64 fixes each W4 result (see spread())
     python tests/golden/make_golden.py w5small   # 8 random 3-SAT formulas, n 50, m 150, chi 32
+    python tests/golden/make_golden.py w3   # 8x8x8 3D Ising at the 3 betas, chi 16, plane slices
 """
 import json
 import math
@@ -36,6 +37,26 @@ def w2(out_path):
     json.dump({"workload": "ising2d 64x64 open, J=1, h=0",
                "generator": "paper_2406_09769_amd.inputs.ising_2d(64, 64, beta)",
                "oracle": "oracle.dm.contract_approx(net, chi, env) with default cutoffs",
+               "rows": rows}, open(out_path, "w"), indent=1)
+
+
+def _w3_one(beta):
+    net = inputs.ising_3d(8, 8, 8, beta)
+    t = time.time()
+    st = dm.Stats()
+    v, s = dm.contract_approx(net, 16, 1, stats=st)
+    row = {"beta": beta, "chi": 16, "env": 1, "log_abs": v, "sign": s, "n_eig": st.n_eig,
+           "seconds": time.time() - t}
+    print(json.dumps(row), flush=True)
+    return row
+
+
+def w3(out_path):
+    with Pool(3) as pool:
+        rows = pool.map(_w3_one, inputs.w3_betas())
+    json.dump({"workload": "ising3d 8x8x8 open, J=1, h=0, one z-plane per slice",
+               "generator": "paper_2406_09769_amd.inputs.ising_3d(8, 8, 8, beta)",
+               "oracle": "oracle.dm.contract_approx(net, 16, 1) with default cutoffs",
                "rows": rows}, open(out_path, "w"), indent=1)
 
 
@@ -117,5 +138,7 @@ if __name__ == "__main__":
         batch("w5", 32, 32, os.path.join(HERE, "w5_oracle.json"))
     elif which == "w4spread":
         spread(os.path.join(HERE, "w4_spread.json"))
+    elif which == "w3":
+        w3(os.path.join(HERE, "w3_oracle.json"))
     elif which == "w5small":
         batch("w5small", 8, 32, os.path.join(HERE, "w5_small_oracle.json"))

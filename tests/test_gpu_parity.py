@@ -153,3 +153,19 @@ def test_w2_full_size_against_golden(T):
             print(f"W2 beta={b:.6f} chi={chi} env={env}: gpu {r.log_abs!r} oracle {g['log_abs']!r} diff/N {d:.3e}",
                   flush=True)
             assert r.sign == g["sign"] and d <= TOL
+
+
+def test_w3_full_size_against_golden(T):
+    """8x8x8 open cubic lattice, one z-plane per slice, chi 16, at the three betas; expected
+    values written by tests/golden/make_golden.py from the oracle (about 22 minutes each on
+    8 host threads). Environments reach 2^27 elements: those ops run over the whole chip."""
+    gold = json.load(open(os.path.join(HERE, "golden", "w3_oracle.json")))["rows"]
+    for g in gold:
+        net = inputs.ising_3d(8, 8, 8, g["beta"])
+        h = T.create_network(net)
+        r = T.tn_contract_approx(h, net.slices, g["chi"], g["env"])
+        d = abs(r.log_abs - g["log_abs"]) / net.n_sites
+        print(f"W3 beta={g['beta']} chi={g['chi']}: gpu {r.log_abs!r} oracle {g['log_abs']!r} diff/N {d:.3e}, "
+              f"{r.seconds:.2f} s", flush=True)
+        assert r.sign == g["sign"] and d <= TOL
+        del h
