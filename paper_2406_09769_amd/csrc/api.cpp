@@ -248,7 +248,7 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
   for (size_t q = n_persist; q < n; ++q) {
     for (const Seg &sg : plans[order[q]]->segs) {
       if (sg.kind == 0) HIP_TRY(tn::launch_interp_range(d_nd + q, sg.first, sg.last, kp, st));
-      else if (sg.kind == 1) HIP_TRY(tn::launch_gemm_grid(d_nd + q, sg.first, sg.blocks, st));
+      else if (sg.kind == 1) HIP_TRY(tn::launch_gemm_grid(d_nd + q, sg.first, sg.blocks, kp.split, st));
       else HIP_TRY(tn::launch_rescale_grid(d_nd + q, sg.first, sg.blocks, d_part, st));
     }
   }

@@ -462,6 +462,7 @@ __device__ void gemm_split(const Op &op, const double *__restrict__ A, const dou
 }
 
 __device__ double block_max(double v, double *red);
+__device__ __forceinline__ double wave_max(double v);
 
 // 2^-e with e the frexp exponent of max |x| over a valid box (1 for an all-zero box)
 __device__ double pow2_scale(double amax) {
@@ -469,6 +470,143 @@ __device__ double pow2_scale(double amax) {
   int e;
   frexp(amax, &e);
   return ldexp(1.0, -e);
+}
+
+// Split-precision counterpart of gemm_tiles for chip-wide ops: 64x64 output tiles in a
+// grid stride, 16-deep k chunks. Each chunk of A (64 x 16) and B (16 x 64) gets its own
+// power-of-two scale (max |x| of the chunk into [1/2, 1)), is split into three parts in
+// LDS, and its six part products accumulate in FP32 for that chunk only; the chunk's
+// sum is scaled back and added to an FP64 accumulator.
+template <int SPLIT>
+__device__ void gemm_split_tiles(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
+                                 double *__restrict__ C, const int32_t *__restrict__ tab, double *lds,
+                                 int t_begin, int t_step, NetScalars *sc) {
+  const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
+  const int NS = op.bn.n;
+  if (t_begin == 0 && threadIdx.x == 0) sc->flops += 2LL * M * N * K;
+  constexpr int P = 20;                                  // 16 parts + 4 pad per row / column
+  unsigned short *a3 = reinterpret_cast<unsigned short *>(lds);   // 3 planes x 64 rows x P
+  unsigned short *b3 = a3 + 3 * 64 * P;                            // 3 planes x 64 cols x P
+  double *red = lds + 2 * kTK * kPitch - 8;
+  int32_t *kA = reinterpret_cast<int32_t *>(lds + 2 * kTK * kPitch);
+  int32_t *kB = kA + kKCache;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const bool kcached = K <= kKCache;
+  if (kcached) {
+    for (int k = tid; k < K; k += kThreads) {
+      const int ks = box_conv(op.bk_, k);
+      kA[k] = tab[op.ak + ks];
+      kB[k] = tab[op.bk + ks];
+    }
+    __syncthreads();
+  }
+  const int tilesN = (N + 63) / 64, ntiles = ((M + 63) / 64) * tilesN;
+  constexpr int NACC = SPLIT == 1 ? 1 : 3;
+  constexpr int O1 = NACC > 1 ? 1 : 0, O2 = NACC > 1 ? 2 : 0;
+  for (int tile = t_begin; tile < ntiles; tile += t_step) {
+    const int m0 = (tile / tilesN) * 64, n0 = (tile % tilesN) * 64;
+    // this thread's 4 A elements (row i, k) and 4 B elements (k, col j) of every chunk
+    int64_t aoff[4], boff[4];
+    int ai[4], ak[4], bj[4], bk[4];
+    bool av[4], bv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + kThreads * q;
+      ai[q] = e >> 4; ak[q] = e & 15;
+      av[q] = m0 + ai[q] < M;
+      aoff[q] = av[q] ? map_off(tab, op.am, box_conv(op.bm, m0 + ai[q])) : 0;
+      bj[q] = e >> 4; bk[q] = e & 15;
+      bv[q] = n0 + bj[q] < N;
+      boff[q] = bv[q] ? map_off(tab, op.bn, box_conv(op.bnb, n0 + bj[q])) : 0;
+    }
+    double acc64[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      double va[4], vb[4];
+      double am = 0.0, bm = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + ak[q], kb = k0 + bk[q];
+        va[q] = (av[q] && k < K) ? A[aoff[q] + (kcached ? kA[k] : tab[op.ak + box_conv(op.bk_, k)])] : 0.0;
+        vb[q] = (bv[q] && kb < K) ? B[boff[q] + (kcached ? kB[kb] : tab[op.bk + box_conv(op.bk_, kb)])] : 0.0;
+        am = fmax(am, fabs(va[q]));
+        bm = fmax(bm, fabs(vb[q]));
+      }
+      am = wave_max(am);
+      bm = wave_max(bm);
+      if (lane == 0) { red[wave] = am; red[4 + wave] = bm; }
+      __syncthreads();
+      const double sa = pow2_scale(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+      const double sb = pow2_scale(fmax(fmax(red[4], red[5]), fmax(red[6], red[7])));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        unsigned short h, m, l;
+        split3<SPLIT>(va[q] * sa, h, m, l);
+        a3[ai[q] * P + ak[q]] = h;
+        a3[(64 + ai[q]) * P + ak[q]] = m;
+        a3[(128 + ai[q]) * P + ak[q]] = l;
+        split3<SPLIT>(vb[q] * sb, h, m, l);
+        b3[bj[q] * P + bk[q]] = h;
+        b3[(64 + bj[q]) * P + bk[q]] = m;
+        b3[(128 + bj[q]) * P + bk[q]] = l;
+      }
+      __syncthreads();
+      const int kq = 4 * (lane >> 4);
+      unsigned long long ah[2], amid[2], al[2], bh[2], bmid[2], bl[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int r = wm * 32 + a * 16 + (lane & 15);
+        ah[a] = *reinterpret_cast<const unsigned long long *>(a3 + r * P + kq);
+        amid[a] = *reinterpret_cast<const unsigned long long *>(a3 + (64 + r) * P + kq);
+        al[a] = *reinterpret_cast<const unsigned long long *>(a3 + (128 + r) * P + kq);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int c = wn * 32 + b * 16 + (lane & 15);
+        bh[b] = *reinterpret_cast<const unsigned long long *>(b3 + c * P + kq);
+        bmid[b] = *reinterpret_cast<const unsigned long long *>(b3 + (64 + c) * P + kq);
+        bl[b] = *reinterpret_cast<const unsigned long long *>(b3 + (128 + c) * P + kq);
+      }
+      const double unscale = 1.0 / (sa * sb);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          v4f acc[NACC];
+#pragma unroll
+          for (int o = 0; o < NACC; ++o) acc[o] = v4f{0.f, 0.f, 0.f, 0.f};
+          acc[O2] = mfma16<SPLIT>(amid[a], bmid[b], acc[O2]);
+          acc[O2] = mfma16<SPLIT>(al[a], bh[b], acc[O2]);
+          acc[O2] = mfma16<SPLIT>(ah[a], bl[b], acc[O2]);
+          acc[O1] = mfma16<SPLIT>(amid[a], bh[b], acc[O1]);
+          acc[O1] = mfma16<SPLIT>(ah[a], bmid[b], acc[O1]);
+          acc[0] = mfma16<SPLIT>(ah[a], bh[b], acc[0]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double v = double(acc[0][r]);
+            if (NACC > 1) v += double(acc[O1][r]) * 0x1p-11 + double(acc[O2][r]) * 0x1p-22;
+            acc64[a][b][r] += v * unscale;
+          }
+        }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * 32 + a * 16 + 4 * (lane >> 4) + r;
+          const int col = n0 + wn * 32 + b * 16 + (lane & 15);
+          if (row < M && col < N) C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = acc64[a][b][r];
+        }
+  }
 }
 
 // LDS doubles of the two stages of a gemm_piped configuration
@@ -1351,7 +1489,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
 
 constexpr int kGridLds = 2 * kTK * kPitch + kKCache;   // gemm_tiles: two k-slices and both k caches
 
-__global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__restrict__ ndp, int64_t i) {
+__global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__restrict__ ndp, int64_t i, int split) {
   __shared__ double lds[kGridLds];
   __shared__ Op s_op;
   const NetDev nd = *ndp;
@@ -1359,7 +1497,9 @@ __global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__res
   const Op &op = s_op;
   const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
   const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-  gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
+  if (split == 1) gemm_split_tiles<1>(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
+  else if (split == 2) gemm_split_tiles<2>(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
+  else gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
 }
 
 // max |x| over this workgroup's share of the valid box -> partial[blockIdx.x]
@@ -1423,8 +1563,8 @@ hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, hipStream_t stream) {
-  hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);
+hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, hipStream_t stream) {
+  hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i, split);
   return hipGetLastError();
 }
 

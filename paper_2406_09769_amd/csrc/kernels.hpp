@@ -47,7 +47,7 @@ hipError_t launch_interp(const NetDev *nets_dev, int n_nets, const KeepParams &k
 constexpr int kGridBlocks = 2048;
 hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last, const KeepParams &kp,
                                hipStream_t stream);
-hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, hipStream_t stream);
+hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, hipStream_t stream);
 hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, double *partial, hipStream_t stream);
 
 }  // namespace tn

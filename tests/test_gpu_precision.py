@@ -33,6 +33,7 @@ def T():
     (lambda: inputs.ising_2d(6, 6, 0.44), 16, 1),
     (lambda: inputs.ising_2d(16, 16, 0.44), 16, 2),
     (lambda: inputs.ising_3d(4, 4, 4, 0.2217), 8, 1),
+    (lambda: inputs.ising_3d(5, 5, 5, 0.2217), 16, 1),     # chip-wide ops: per-chunk scaling
     (lambda: inputs.ising_rrg(40, 1.0, 4100), 16, 1),
 ])
 def test_precision_form_within_bound(T, precision, net_fn, chi, env):
@@ -71,3 +72,18 @@ def test_w2_full_size_precision_form(T, precision):
           f"per (chi, env) group {[f'{max(errs[8 * i:8 * i + 8]):.1e}' for i in range(4)]}", flush=True)
     assert all(r.sign == g["sign"] for r, g in zip(rs, gl))
     assert max(errs) <= BOUND
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_w3_full_size_precision_form(T, precision):
+    """8x8x8 lattice, chi 16, the three betas, against the stored FP64 oracle values."""
+    gold = json.load(open(os.path.join(HERE, "golden", "w3_oracle.json")))["rows"]
+    for g in gold:
+        net = inputs.ising_3d(8, 8, 8, g["beta"])
+        h = T.create_network(net)
+        r = T.tn_contract_approx(h, net.slices, g["chi"], g["env"], precision=precision)
+        d = abs(r.log_abs - g["log_abs"]) / net.n_sites
+        print(f"W3 beta={g['beta']} chi={g['chi']} precision={precision}: |dlnZ|/N {d:.3e}, {r.seconds:.2f} s",
+              flush=True)
+        assert r.sign == g["sign"] and d <= BOUND
+        del h
