@@ -170,11 +170,14 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
 // buffers: while the waves multiply step s out of one buffer, every thread already
 // holds its loads of step s+1 (possibly the next block) in registers. Offsets are
 // resolved once per op into LDS: kA/kB (k), rA (A row), cB (B column), rC/cC (C).
-template <int MB, int NB, int KC, int TM, int TN>
+// GRID: one of many workgroups on a chip-wide op. It takes the blocks [b_begin, b_end)
+// (columns fastest) and resolves column offsets on the fly from the index tables
+// (cB and cC unused); row and k offsets are still cached in LDS.
+template <int MB, int NB, int KC, int TM, int TN, bool GRID = false>
 __device__ void gemm_piped(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
                            double *__restrict__ C, double *lds, int M, int N, int K, const int32_t *kA,
                            const int32_t *kB, const int32_t *rA, const int32_t *cB, const int32_t *rC,
-                           const int32_t *cC) {
+                           const int32_t *cC, const int32_t *tab = nullptr, int b_begin = 0, int b_end = -1) {
   constexpr int WN = NB / (16 * TN);               // waves along N
   static_assert((MB / (16 * TM)) * WN == 4, "4 waves per block");
   constexpr int PA = MB + 1, PB = NB + 1;          // LDS pitches of a k row
@@ -186,7 +189,18 @@ __device__ void gemm_piped(const Op &op, const double *__restrict__ A, const dou
   const bool akf = (op.flags & F_A_KFAST) != 0;
   const bool bnf = (op.flags & F_B_NFAST) != 0;
   const int nbm = (M + MB - 1) / MB, nbn = (N + NB - 1) / NB, nch = (K + KC - 1) / KC;
-  const int steps = nbm * nbn * nch;
+  const int nblk = nbm * nbn;
+  const int blk_hi = (b_end < 0 || b_end > nblk) ? nblk : b_end;
+  const int s_begin = b_begin * nch;
+  const int steps = blk_hi > b_begin ? blk_hi * nch : 0;
+  auto colB = [&](int n) -> int64_t {
+    if constexpr (GRID) return map_off(tab, op.bn, box_conv(op.bnb, n));
+    else return cB[n];
+  };
+  auto colC = [&](int n) -> int64_t {
+    if constexpr (GRID) return box_conv(op.bnb, n);
+    else return cC[n];
+  };
   double ra[LA], rb[LB];
   auto load = [&](int s) {
     const int blk = s / nch, ch = s - blk * nch;
@@ -204,7 +218,7 @@ __device__ void gemm_piped(const Op &op, const double *__restrict__ A, const dou
       const int e = tid + kThreads * q;
       const int j = bnf ? e % NB : e / KC, k = bnf ? e / NB : e % KC;
       double y = 0.0;
-      if (e < KC * NB && n0 + j < N && k0 + k < K) y = B[int64_t(cB[n0 + j]) + kB[k0 + k]];
+      if (e < KC * NB && n0 + j < N && k0 + k < K) y = B[colB(n0 + j) + kB[k0 + k]];
       rb[q] = y;
     }
   };
@@ -228,8 +242,8 @@ __device__ void gemm_piped(const Op &op, const double *__restrict__ A, const dou
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-  if (steps > 0) load(0);
-  for (int s = 0; s < steps; ++s) {
+  if (steps > s_begin) load(s_begin);
+  for (int s = s_begin; s < steps; ++s) {
     const int buf = s & 1;
     stash(buf);
     __syncthreads();
@@ -260,7 +274,7 @@ __device__ void gemm_piped(const Op &op, const double *__restrict__ A, const dou
           for (int r = 0; r < 4; ++r) {
             const int row = m0 + wm * TM * 16 + a * 16 + (lane >> 4) + 4 * r;   // D: lane l, reg r = row l/16 + 4r
             const int col = n0 + wn * TN * 16 + b * 16 + (lane & 15);
-            if (row < M && col < N) C[int64_t(rC[row]) + cC[col]] = acc[a][b][r];
+            if (row < M && col < N) C[int64_t(rC[row]) + colC(col)] = acc[a][b][r];
           }
           acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
         }
@@ -906,27 +920,38 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
 
   double *Z = A;
   for (int e = tid; e < n * n; e += kThreads) Z[e] = (e / n == e % n) ? 1.0 : 0.0;
-  // Every wave that owns rows of Z (and wave 0, whose copy yields the eigenvalues)
-  // runs the same chase on a private copy of (d, e) in LDS, so no barrier is needed
-  // inside the iteration. Within a sweep step i reads d[i], e[i] and writes index
-  // i+1, so the reads of the next step are issued one step ahead.
-  double *wd = E.wq + 2 * n * wave, *we = wd + n;
-  for (int i = lane; i < n; i += 64) { wd[i] = dd[i]; we[i] = ee[i]; }
+  // Implicit QL, split between a producer and consumers. Wave 0 runs the chase on its
+  // own LDS copy of (d, e) (a sweep step reads index i and writes i+1, so the next
+  // step's reads are issued one step ahead) and records the (c, s) of every rotation
+  // of one QL iteration; after a barrier waves 1-3 apply that iteration's rotations to
+  // their rows of Z while wave 0 already chases the next iteration into the other
+  // buffer. One barrier per QL iteration; the chase carries no Z traffic.
+  double *wd = E.wq, *we = wd + n;
+  double *rot = E.wq + 2 * n;                       // two buffers of n (c, s) pairs
+  int *meta = E.flag;                               // per buffer: m, rotations (-1: finished)
+  for (int i = tid; i < n; i += kThreads) { wd[i] = dd[i]; we[i] = ee[i]; }
   __syncthreads();
-  const int row = tid;
-  const bool own = row < n;
   constexpr double kEps = 2.220446049250313e-16;
   long long nrot = 0;
-  if (wave == 0 || wave * 64 < n) {
+  // producer state (wave 0)
+  int l = 0, iter = 0;
+  double efloor = 0.0;
+  if (wave == 0) {
     // absolute deflation floor: an off-diagonal below eps*||T|| is negligible at the
     // absolute accuracy of any backward-stable solver; without it the null space of a
     // rank-deficient density matrix is iterated to full relative precision
     double tn = 0.0;
     for (int i = lane; i < n; i += 64) tn = fmax(tn, fmax(fabs(wd[i]), 2.0 * fabs(we[i])));
-    const double efloor = kEps * wave_max(tn);
-    for (int l = 0; l < n; ++l) {
-      for (int iter = 0; iter < 64; ++iter) {
-        int m = n - 1;                               // first m >= l with a negligible e[m]
+    efloor = kEps * wave_max(tn);
+  }
+  const int crow = tid - 64;                        // consumer row
+  const bool own = wave > 0 && crow < n;
+  for (int b = 0;; b ^= 1) {
+    if (wave == 0) {
+      int m = -1;
+      while (l < n) {
+        if (iter >= 64) { ++l; iter = 0; continue; }
+        m = n - 1;                                  // first m >= l with a negligible e[m]
         for (int base = l; base < n - 1; base += 64) {
           const int i = base + lane;
           bool small = false;
@@ -937,57 +962,72 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
           const unsigned long long bl = __ballot(small);
           if (bl) { m = base + __ffsll((long long)bl) - 1; break; }
         }
-        if (m == l) break;
+        if (m != l) break;
+        ++l;
+        iter = 0;
+      }
+      if (l >= n) {
+        if (lane == 0) { meta[2 * b] = 0; meta[2 * b + 1] = -1; }
+      } else {
+        ++iter;
+        double *rb = rot + 2 * n * b;
         const double dl = wd[l], el = we[l];
         double g = (wd[l + 1] - dl) / (2.0 * el);
         double r = sqrt(g * g + 1.0);
         g = wd[m] - dl + el / (g + copysign(r, g));
         double s = 1.0, c = 1.0, p = 0.0;
-        double zc = own ? Z[m * n + row] : 0.0;       // current value of column i+1
-        double zn = own ? Z[(m - 1) * n + row] : 0.0; // column i, fetched one step ahead
         double di1 = wd[m];
-        double en = we[m - 1], dn = wd[m - 1];        // e[i], d[i], fetched one step ahead
-        int i = m - 1;
+        double en = we[m - 1], dn = wd[m - 1];      // e[i], d[i], fetched one step ahead
+        int i = m - 1, cnt = 0;
         bool split = false;
         for (; i >= l; --i) {
-          const double ei = en, di = dn, zi = zn;
-          if (i > l) {
-            en = we[i - 1];
-            dn = wd[i - 1];
-            if (own) zn = Z[(i - 1) * n + row];
-          }
+          const double ei = en, di = dn;
+          if (i > l) { en = we[i - 1]; dn = wd[i - 1]; }
           ++nrot;
-          const double f = s * ei, b = c * ei;
+          const double f = s * ei, bb = c * ei;
           const double q = f * f + g * g;
-          if (q == 0.0) {                                // underflow: T splits here
+          if (q == 0.0) {                              // underflow: T splits here
             if (lane == 0) { we[i + 1] = 0.0; wd[i + 1] = di1 - p; we[m] = 0.0; }
             split = true;
             break;
           }
-          const double rr = rsqrt_nr(q);                // 1/sqrt(f^2 + g^2)
+          const double rr = rsqrt_nr(q);              // 1/sqrt(f^2 + g^2)
           r = q * rr;
           s = f * rr;
           c = g * rr;
           g = di1 - p;
-          const double t = (di - g) * s + 2.0 * c * b;
+          const double t = (di - g) * s + 2.0 * c * bb;
           p = s * t;
           const double dnew = g + p;
-          g = c * t - b;
-          if (lane == 0) { we[i + 1] = r; wd[i + 1] = dnew; }
+          g = c * t - bb;
+          if (lane == 0) { we[i + 1] = r; wd[i + 1] = dnew; rb[2 * cnt] = c; rb[2 * cnt + 1] = s; }
+          ++cnt;
           di1 = di;
-          if (own) {
-            Z[(i + 1) * n + row] = s * zi + c * zc;
-            zc = c * zi - s * zc;
-          }
         }
-        if (own) Z[(i + 1) * n + row] = zc;
-        if (split) continue;
-        if (lane == 0) { wd[l] = dl - p; we[l] = g; we[m] = 0.0; }
+        if (!split && lane == 0) { wd[l] = dl - p; we[l] = g; we[m] = 0.0; }
+        if (lane == 0) { meta[2 * b] = m; meta[2 * b + 1] = cnt; }
       }
+    }
+    __syncthreads();
+    const int m = meta[2 * b], cnt = meta[2 * b + 1];
+    if (cnt < 0) break;
+    if (own && cnt > 0) {                            // apply the iteration's rotations to row crow
+      const double *rb = rot + 2 * n * b;
+      double zc = Z[m * n + crow];                   // current value of column i+1
+      double zn = Z[(m - 1) * n + crow];             // column i, fetched one step ahead
+      for (int j = 0; j < cnt; ++j) {
+        const int i = m - 1 - j;
+        const double zi = zn;
+        if (j + 1 < cnt) zn = Z[(i - 1) * n + crow];
+        const double c = rb[2 * j], s = rb[2 * j + 1];
+        Z[(i + 1) * n + crow] = s * zi + c * zc;
+        zc = c * zi - s * zc;
+      }
+      Z[(m - cnt) * n + crow] = zc;
     }
   }
   __syncthreads();
-  for (int i = tid; i < n; i += kThreads) dd[i] = E.wq[i];     // wave 0's eigenvalues
+  for (int i = tid; i < n; i += kThreads) dd[i] = wd[i];     // the eigenvalues
   if (tid == 0) sc->n_rot += nrot;
   __syncthreads();
   if (timed && tid == 0) sc->ticks[6] += wall_clock64() - tph;
@@ -1488,15 +1528,61 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
 // elements in a stride of the grid.
 
 constexpr int kGridLds = 2 * kTK * kPitch + kKCache;   // gemm_tiles: two k-slices and both k caches
+constexpr int kGridPipedTiles = piped_stage_doubles(32, 128, 16);   // largest chip-wide piped configuration
+constexpr int kGridLdsAll = kGridLds > kGridPipedTiles + 1216 ? kGridLds : kGridPipedTiles + 1216;
+
+// FP64 chip-wide GEMM through the pipelined path: k and row offsets cached in LDS,
+// each workgroup a contiguous range of output blocks. False if the caches do not fit.
+__device__ bool gemm_grid_piped(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
+                                double *__restrict__ C, const int32_t *__restrict__ tab, double *lds,
+                                NetScalars *sc) {
+  const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
+  if (2 * (int64_t(M) + K) > 2 * int64_t(kGridLdsAll - kGridPipedTiles)) return false;
+  const int64_t NS = op.bn.n;
+  if (int64_t(op.am.n) * NS >= (int64_t(1) << 31)) return false;   // row offsets of C as int32
+  int32_t *kA = reinterpret_cast<int32_t *>(lds + kGridPipedTiles);
+  int32_t *kB = kA + K, *rA = kB + K, *rC = rA + M;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) sc->flops += 2LL * M * N * K;
+  for (int k = tid; k < K; k += kThreads) {
+    const int ks = box_conv(op.bk_, k);
+    kA[k] = tab[op.ak + ks];
+    kB[k] = tab[op.bk + ks];
+  }
+  for (int m = tid; m < M; m += kThreads) {
+    const int sm = box_conv(op.bm, m);
+    rA[m] = int32_t(map_off(tab, op.am, sm));
+    rC[m] = int32_t(sm * NS);
+  }
+  __syncthreads();
+  auto range = [&](int nblk, int &b0, int &b1) {
+    const int per = (nblk + int(gridDim.x) - 1) / int(gridDim.x);
+    b0 = int(blockIdx.x) * per;
+    b1 = b0 + per;
+  };
+  int b0, b1;
+  if (M <= 16) {
+    range(((N + 255) / 256), b0, b1);
+    gemm_piped<16, 256, 8, 1, 4, true>(op, A, B, C, lds, M, N, K, kA, kB, rA, nullptr, rC, nullptr, tab, b0, b1);
+  } else if (M <= 32) {
+    range(((N + 127) / 128), b0, b1);
+    gemm_piped<32, 128, 16, 2, 2, true>(op, A, B, C, lds, M, N, K, kA, kB, rA, nullptr, rC, nullptr, tab, b0, b1);
+  } else {
+    range(((M + 63) / 64) * ((N + 63) / 64), b0, b1);
+    gemm_piped<64, 64, 16, 2, 2, true>(op, A, B, C, lds, M, N, K, kA, kB, rA, nullptr, rC, nullptr, tab, b0, b1);
+  }
+  return true;
+}
 
 __global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__restrict__ ndp, int64_t i, int split) {
-  __shared__ double lds[kGridLds];
+  __shared__ double lds[kGridLdsAll];
   __shared__ Op s_op;
   const NetDev nd = *ndp;
   stage_op(nd, i, s_op);
   const Op &op = s_op;
   const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
   const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
+  if (split == 0 && gemm_grid_piped(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc)) return;
   if (split == 1) gemm_split_tiles<1>(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
   else if (split == 2) gemm_split_tiles<2>(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
   else gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);

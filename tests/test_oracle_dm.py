@@ -344,3 +344,20 @@ def test_pins_catch_an_unprimed_bra(monkeypatch):
     except AssertionError:
         caught = True                       # the oracle's own label checks fire
     assert caught
+
+
+def test_result_does_not_depend_on_the_lapack_driver_on_lattices():
+    """The method's value on a lattice is fixed by FP64 arithmetic: swapping the oracle's
+    symmetric eigensolver (divide and conquer) for LAPACK's MRRR driver moves lnZ by
+    rounding only. (On signed random graphs it does not; the GPU tests then bound the
+    error by the spread this swap produces.)"""
+    import scipy.linalg as sl
+    net = inputs.ising_2d(10, 10, 0.44)
+    v0, s0 = dm.contract_approx(net, 8, 1)
+    old = dm.EIGH
+    dm.EIGH = lambda L: sl.eigh(L, driver="evr")
+    try:
+        v1, s1 = dm.contract_approx(net, 8, 1)
+    finally:
+        dm.EIGH = old
+    assert s0 == s1 and abs(v0 - v1) / net.n_sites < 1e-13
