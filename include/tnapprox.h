@@ -87,6 +87,10 @@ typedef struct {
   double tau_deg;         /* clusters with gap <= tau_deg * w1 are never split */
   void *hip_stream;       /* hipStream_t the work is queued on (NULL = null stream) */
   tn_model model;         /* learned mode: the MLP that ranks the warm-start columns */
+  int32_t gemm_config[3]; /* FP64 contraction block shape for ops of <= 16, <= 32 and more
+                             rows: 0 = built-in, k = 1..6 the k-th of 16x512/k8, 16x256/k16,
+                             32x128/k32, 32x128/k16, 64x64/k32, 64x64/k16 (the autotuner's
+                             choices, paper_2406_09769_amd/autotune.py) */
 } tn_options;
 
 /* Result of one contraction. log_abs = ln|Z| (natural log), sign in {-1, 0, +1};

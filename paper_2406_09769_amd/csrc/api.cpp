@@ -344,9 +344,12 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int
   if (o.eig == TN_EIG_LEARNED && !o.model) return fail(TN_EINVAL, "learned eigensolve needs a model");
   if (o.eig == TN_EIG_LEARNED && !(o.residual_tol > 0)) return fail(TN_EINVAL, "residual_tol must be > 0");
   if (!(o.tau_rel >= 0) || !(o.tau_deg >= 0)) return fail(TN_EINVAL, "tau_rel and tau_deg must be >= 0");
+  for (int c = 0; c < 3; ++c)
+    if (o.gemm_config[c] < 0 || o.gemm_config[c] > tn::kGemmConfigs) return fail(TN_EINVAL, "gemm_config out of range");
   tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
   kp.residual_tol = o.residual_tol;
   kp.split = int(o.precision);
+  for (int c = 0; c < 3; ++c) kp.gemm_cfg[c] = o.gemm_config[c];
   if (o.eig == TN_EIG_LEARNED) kp.model = o.model->d_w;
   return contract_batch(nets, paths, max_ranks, env_sizes, n, o, kp, outs);
 }

@@ -634,7 +634,7 @@ static_assert(2 * split_stage_words(16, 256, 16) <= 4 * (kPipedTiles - 8), "spli
 // then runs gemm_tiles).
 __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
                         double *__restrict__ C, const int32_t *__restrict__ tab, double *lds, NetScalars *sc,
-                        int split) {
+                        int split, const int *cfgs) {
   const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
   const int64_t NS = op.bn.n;
   if (2 * (int64_t(M) + N + K) > 2 * int64_t(kLdsDoubles - kPipedTiles)) return false;
@@ -675,12 +675,18 @@ __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double
     }
     return true;
   }
-  if (M <= 16)
-    gemm_piped<16, 512, 8, 1, 8>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC);
-  else if (M <= 32)
-    gemm_piped<32, 128, 32, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC);
-  else
-    gemm_piped<64, 64, 32, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC);
+  // block configuration: the option's choice for this row class, else 16x512 / 32x128 / 64x64
+  const int cls = M <= 16 ? 0 : (M <= 32 ? 1 : 2);
+  int cfg = cfgs[cls] - 1;
+  if (cfg < 0 || cfg >= kGemmConfigs) cfg = cls == 0 ? 0 : (cls == 1 ? 2 : 4);
+  switch (cfg) {
+    case 0: gemm_piped<16, 512, 8, 1, 8>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC); break;
+    case 1: gemm_piped<16, 256, 16, 1, 4>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC); break;
+    case 2: gemm_piped<32, 128, 32, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC); break;
+    case 3: gemm_piped<32, 128, 16, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC); break;
+    case 4: gemm_piped<64, 64, 32, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC); break;
+    default: gemm_piped<64, 64, 16, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC); break;
+  }
   return true;
 }
 
@@ -1497,7 +1503,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
       case OP_GEMM: {
         const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
         const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-        if (!gemm_op(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc, kp.split))
+        if (!gemm_op(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc, kp.split, kp.gemm_cfg))
           gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1, nd.sc);
         break;
       }

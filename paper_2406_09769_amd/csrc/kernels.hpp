@@ -29,7 +29,13 @@ struct KeepParams {
   int *hcount;             // harvest: rows written so far (atomic)
   long long hcap;          // harvest: capacity in rows
   int split;               // contraction precision: 0 FP64, 1 BF16 x3 split, 2 FP16 x3 split
+  int gemm_cfg[3];         // FP64 GEMM block configuration for ops of <= 16, <= 32, > 32 rows:
+                           // 0 = built-in choice, k = candidate k-1 of kGemmConfigs
 };
+
+// The FP64 pipelined GEMM's candidate block configurations (rows x columns per block,
+// k chunk), in the order the options and the autotuner number them.
+constexpr int kGemmConfigs = 6;
 
 constexpr double kClusterFloor = 1e-10;
 constexpr int kMlpParams = 8 * 32 + 32 + 32 * 32 + 32 + 32 + 1;   // 8 -> 32 -> 32 -> 1

@@ -43,7 +43,7 @@ class tn_path(C.Structure):
 class tn_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eig", C.c_int32), ("residual_tol", C.c_double),
                 ("tau_rel", C.c_double), ("tau_deg", C.c_double), ("hip_stream", C.c_void_p),
-                ("model", C.c_void_p)]
+                ("model", C.c_void_p), ("gemm_config", C.c_int32 * 3)]
 
 
 class tn_result(C.Structure):
@@ -145,9 +145,10 @@ class _PathArgs:
 
 
 def _options(precision=TN_FP64, eig=TN_EIG_EXACT, residual_tol=1e-6, tau_rel=1e-15, tau_deg=1e-12,
-             stream=None, model=None):
+             stream=None, model=None, gemm_config=(0, 0, 0)):
     return tn_options(int(precision), int(eig), float(residual_tol), float(tau_rel), float(tau_deg),
-                      C.c_void_p(stream) if stream else None, model.ptr if model is not None else None)
+                      C.c_void_p(stream) if stream else None, model.ptr if model is not None else None,
+                      (C.c_int32 * 3)(*[int(x) for x in gemm_config]))
 
 
 @dataclass

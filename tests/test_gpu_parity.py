@@ -155,6 +155,18 @@ def test_w2_full_size_against_golden(T):
             assert r.sign == g["sign"] and d <= TOL
 
 
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5, 6])
+def test_every_gemm_block_configuration(T, cfg):
+    """The autotuner's candidates all compute the same contraction: force one block
+    configuration for every row class (16x16 lattice, env 1 and 2)."""
+    net = inputs.ising_2d(16, 16, 0.44)
+    h = T.create_network(net)
+    for env in (1, 2):
+        r = T.tn_contract_approx(h, net.slices, 16, env, gemm_config=(cfg, max(cfg, 3), max(cfg, 3)))
+        v, s = dm.contract_approx(net, 16, env)
+        assert r.sign == s and abs(r.log_abs - v) / net.n_sites <= TOL
+
+
 def test_w3_full_size_against_golden(T):
     """8x8x8 open cubic lattice, one z-plane per slice, chi 16, at the three betas; expected
     values written by tests/golden/make_golden.py from the oracle (about 22 minutes each on
