@@ -42,7 +42,12 @@ struct DevPlan {
   std::vector<Seg> segs;     // empty: the whole network fits one workgroup's pass
   tn::Op *d_ops = nullptr;
   int32_t *d_tab = nullptr;
+  // the launches of `segs`, captured once as a HIP graph, and what they were captured
+  // with (the launch parameters; the network's descriptor is read at run time)
+  hipGraphExec_t gexec = nullptr;
+  std::vector<char> gkey;
   ~DevPlan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
     if (d_ops) (void)hipFree(d_ops);
     if (d_tab) (void)hipFree(d_tab);
   }
@@ -86,8 +91,16 @@ struct tn_net_s {
   int64_t ws_cap = 0;
   tn::NetScalars *d_sc = nullptr;
   std::map<PlanKey, std::unique_ptr<DevPlan>> plans;
+  // for networks run op by op: a device copy of the network's descriptor, the grid
+  // scratch and a stream to capture the op launches on (all kept while the handle lives)
+  tn::NetDev *d_nd = nullptr;
+  double *d_part = nullptr;
+  hipStream_t cap_stream = nullptr;
   ~tn_net_s() {
     plans.clear();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (d_nd) (void)hipFree(d_nd);
+    if (d_part) (void)hipFree(d_part);
     if (d_const) (void)hipFree(d_const);
     if (d_ws) (void)hipFree(d_ws);
     if (d_sc) (void)hipFree(d_sc);
@@ -205,9 +218,53 @@ tn_options defaults() {
   return o;
 }
 
+// The op launches of a network that runs op by op, on stream st.
+int launch_segments(tn_net net, DevPlan *dp, const tn::KeepParams &kp, hipStream_t st) {
+  for (const Seg &sg : dp->segs) {
+    if (sg.kind == 0) HIP_TRY(tn::launch_interp_range(net->d_nd, sg.first, sg.last, kp, st));
+    else if (sg.kind == 1) HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, sg.blocks, kp.split, st));
+    else HIP_TRY(tn::launch_rescale_grid(net->d_nd, sg.first, sg.blocks, net->d_part, st));
+  }
+  return TN_OK;
+}
+
+// Run a network op by op: its launches are captured once into a HIP graph (per plan
+// and launch parameters) and the graph is launched on st.
+int run_stepwise(tn_net net, DevPlan *dp, const tn::NetDev &nd, const tn::KeepParams &kp, hipStream_t st) {
+  if (!net->d_nd && hipMalloc(&net->d_nd, sizeof(tn::NetDev)) != hipSuccess)
+    return fail(TN_ENOMEM, "descriptor allocation failed");
+  if (!net->d_part && hipMalloc(&net->d_part, tn::kGridBlocks * sizeof(double)) != hipSuccess)
+    return fail(TN_ENOMEM, "grid scratch allocation failed");
+  HIP_TRY(hipMemcpyAsync(net->d_nd, &nd, sizeof(nd), hipMemcpyHostToDevice, st));
+  std::vector<char> key;                    // the launch parameters, field by field (no padding)
+  auto put = [&key](const void *p, size_t b) {
+    const char *c = static_cast<const char *>(p);
+    key.insert(key.end(), c, c + b);
+  };
+  put(&kp.tau_rel, 8); put(&kp.tau_deg, 8); put(&kp.floor, 8); put(&kp.residual_tol, 8);
+  put(&kp.model, sizeof(kp.model)); put(&kp.hx, sizeof(kp.hx)); put(&kp.hy, sizeof(kp.hy));
+  put(&kp.hcount, sizeof(kp.hcount)); put(&kp.hcap, 8); put(&kp.split, 4); put(kp.gemm_cfg, 12);
+  if (!dp->gexec || dp->gkey != key) {
+    if (dp->gexec) { (void)hipGraphExecDestroy(dp->gexec); dp->gexec = nullptr; }
+    if (!net->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_segments(net, dp, kp, net->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(net->cap_stream, &graph);
+    if (rc != TN_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (ec != hipSuccess) return fail(TN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&dp->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) { dp->gexec = nullptr; return fail(TN_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ei)); }
+    dp->gkey = key;
+  }
+  HIP_TRY(hipGraphLaunch(dp->gexec, st));
+  return TN_OK;
+}
+
 // Run a list of prepared networks: those that fit one workgroup's pass in one
 // persistent interpreter launch (one workgroup each), then each larger network op
-// run by op run on the same stream.
+// run by op run (a captured graph) on the same stream.
 int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &plans, const tn_options &o,
               const tn::KeepParams &kp, double *seconds, std::vector<tn::NetScalars> &sc_out) {
   hipStream_t st = reinterpret_cast<hipStream_t>(o.hip_stream);
@@ -233,24 +290,19 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
     nd[q].dyn = reinterpret_cast<int32_t *>(nets[i]->d_ws + plans[i]->plan.dyn_off);
   }
   tn::NetDev *d_nd = nullptr;
-  if (hipMalloc(&d_nd, n * sizeof(tn::NetDev)) != hipSuccess) return fail(TN_ENOMEM, "launch descriptor allocation failed");
-  std::unique_ptr<tn::NetDev, void (*)(tn::NetDev *)> guard(d_nd, [](tn::NetDev *p) { (void)hipFree(p); });
-  double *d_part = nullptr;
-  if (n_persist < n && hipMalloc(&d_part, tn::kGridBlocks * sizeof(double)) != hipSuccess)
-    return fail(TN_ENOMEM, "grid scratch allocation failed");
-  std::unique_ptr<double, void (*)(double *)> guard2(d_part, [](double *p) { if (p) (void)hipFree(p); });
-  HIP_TRY(hipMemcpyAsync(d_nd, nd.data(), n * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
+  if (n_persist > 0 && hipMalloc(&d_nd, n_persist * sizeof(tn::NetDev)) != hipSuccess)
+    return fail(TN_ENOMEM, "launch descriptor allocation failed");
+  std::unique_ptr<tn::NetDev, void (*)(tn::NetDev *)> guard(d_nd, [](tn::NetDev *p) { if (p) (void)hipFree(p); });
+  if (n_persist > 0)
+    HIP_TRY(hipMemcpyAsync(d_nd, nd.data(), n_persist * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, st));
   if (n_persist > 0) HIP_TRY(tn::launch_interp(d_nd, int(n_persist), kp, st));
   for (size_t q = n_persist; q < n; ++q) {
-    for (const Seg &sg : plans[order[q]]->segs) {
-      if (sg.kind == 0) HIP_TRY(tn::launch_interp_range(d_nd + q, sg.first, sg.last, kp, st));
-      else if (sg.kind == 1) HIP_TRY(tn::launch_gemm_grid(d_nd + q, sg.first, sg.blocks, kp.split, st));
-      else HIP_TRY(tn::launch_rescale_grid(d_nd + q, sg.first, sg.blocks, d_part, st));
-    }
+    const int rc = run_stepwise(nets[order[q]], plans[order[q]], nd[q], kp, st);
+    if (rc != TN_OK) return rc;
   }
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipEventSynchronize(e1));

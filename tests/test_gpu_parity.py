@@ -181,3 +181,20 @@ def test_w3_full_size_against_golden(T):
               f"{r.seconds:.2f} s", flush=True)
         assert r.sign == g["sign"] and d <= TOL
         del h
+
+
+def test_chip_wide_network_replays_its_graph(T):
+    """A network with chip-wide ops runs from a captured HIP graph: repeated calls replay it
+    (identical results), a call with other launch parameters captures anew, and going back
+    replays correctly again."""
+    net = inputs.ising_3d(5, 5, 5, 0.2217)
+    h = T.create_network(net)
+    assert T.tn_plan_stats(h, net.slices, 16, 1)["grid_ops"] > 0
+    v, s = dm.contract_approx(net, 16, 1)
+    a = T.tn_contract_approx(h, net.slices, 16, 1)
+    b = T.tn_contract_approx(h, net.slices, 16, 1)
+    c = T.tn_contract_approx(h, net.slices, 16, 1, precision=T.TN_SPLIT_BF16X3)
+    d = T.tn_contract_approx(h, net.slices, 16, 1)
+    assert a.log_abs == b.log_abs == d.log_abs and a.sign == b.sign == d.sign == s
+    assert abs(a.log_abs - v) / net.n_sites <= TOL
+    assert abs(c.log_abs - v) / net.n_sites <= 1e-6 and c.log_abs != a.log_abs
