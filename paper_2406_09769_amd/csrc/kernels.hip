@@ -800,12 +800,13 @@ struct EigWs {          // LDS work area of one solve of order n
   double *vv, *pp, *ww, *dd, *ee, *wsrt;
   int *isrt, *flag;
   double *red;
-  double *wq;           // per wave: its own copy of the tridiagonal (d then e, 2n doubles)
+  double *wq;           // 8n: QL's copy of (d, e) and rotation buffers; then reflector blocks
+  double *gw;           // 24: Gram matrix and betas of a reflector block
   double *hv;           // reflectors in global memory: v_j at hv[j*n + i], beta_j at hv[n*n + j]
   int n, pa;
 };
 
-__host__ __device__ constexpr int eig_lds_doubles(int n) { return n * (n + 1) + 14 * n + (n + 1) / 2 + 8; }
+__host__ __device__ constexpr int eig_lds_doubles(int n) { return n * (n + 1) + 14 * n + (n + 1) / 2 + 8 + 24; }
 static_assert(eig_lds_doubles(128) <= kLdsDoubles, "the largest density matrix fits LDS");
 
 __device__ EigWs eig_ws(double *base, int n, double *hv) {
@@ -823,6 +824,7 @@ __device__ EigWs eig_ws(double *base, int n, double *hv) {
   E.flag = E.isrt + n + (n & 1);
   E.red = reinterpret_cast<double *>(E.flag + 4);
   E.wq = E.red + 4;
+  E.gw = E.wq + 8 * n;
   E.hv = hv;
   return E;
 }
@@ -1067,53 +1069,109 @@ __device__ int keep_rank(const double *w, int navail, int n, int ucols, const Ke
   return k;
 }
 
-// z <- Q z for the k kept columns of Z (E.isrt[0..k)), last reflector first. Dot
-// products run 4 lanes per column with two partial sums per lane; the next
-// reflector is staged into the other buffer during the update, so each reflector
-// costs two barriers.
+// z <- Q z for the k kept columns of Z (E.isrt[0..k)), last reflector first, four
+// reflectors at a time in compact WY form: for the block H_lo ... H_hi (H_hi applied
+// first), Q_blk = I - V T V^T with V = [v_lo .. v_hi] over rows lo+1..n-1 and T upper
+// triangular (T_ii = beta_i, T(1:i-1, i) = -beta_i T(1:i-1, 1:i-1) V(:, 1:i-1)^T v_i).
+// Per block: one phase computes w_t = V^T z_t for every kept column (4 lanes per column,
+// four partial sums) and the Gram matrix V^T V; the next computes T from it in every
+// thread and z_t -= V (T w_t), while the next block's V is staged into the other buffer.
+// Two barriers per four reflectors.
+constexpr int kWY = 4;
 __device__ void back_transform(const EigWs &E, int k) {
   const int n = E.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, sub = tid & 3, grp = tid >> 2;
   double *Z = E.A;
+  double *wbuf = E.vv;                       // k x kWY values of V^T z (vv..ee: 5n doubles)
+  double *G = E.gw, *bet = E.gw + 16;        // Gram matrix of the block, its betas
+  auto stage = [&](int jhi, double *Vb) {    // V of block jhi .. jlo over rows jlo+1..n-1
+    const int jlo = jhi - kWY + 1 > 0 ? jhi - kWY + 1 : 0;
+    const int mlo = n - jlo - 1;
+    for (int e = tid; e < kWY * n; e += kThreads) {
+      const int c = e / n, ip = e % n;       // column c holds v_{jlo+c}, local row ip
+      const int j = jlo + c;
+      double x = 0.0;
+      if (j <= jhi && ip < mlo && ip >= c && E.hv[int64_t(n) * n + j] != 0.0) x = E.hv[int64_t(j) * n + (ip - c)];
+      Vb[c * n + ip] = x;
+    }
+  };
   int cur = 0;
-  int j = n - 3;
-  if (j >= 0) {
-    for (int i = tid; i < n - j - 1; i += kThreads) E.vv[i] = E.hv[int64_t(j) * n + i];
+  if (n >= 3) {
+    stage(n - 3, E.wq);
     __syncthreads();
   }
-  for (; j >= 0; --j) {
-    const int m = n - j - 1;
-    const double beta = E.hv[int64_t(n) * n + j];
-    const double *v = cur ? E.ww : E.vv;
-    double *vnext = cur ? E.vv : E.ww;
-    if (beta != 0.0) {
-      for (int t = grp; t < k; t += kThreads / 4) {
-        const double *z = Z + E.isrt[t] * n + j + 1;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int i = sub;
-        for (; i + 12 < m; i += 16) {
-          a0 += v[i] * z[i];
-          a1 += v[i + 4] * z[i + 4];
-          a2 += v[i + 8] * z[i + 8];
-          a3 += v[i + 12] * z[i + 12];
-        }
-        for (; i < m; i += 4) a0 += v[i] * z[i];
-        double acc = (a0 + a1) + (a2 + a3);
-        acc += __shfl_xor(acc, 1, 64);
-        acc += __shfl_xor(acc, 2, 64);
-        if (sub == 0) E.pp[t] = beta * acc;
+  for (int jhi = n - 3; jhi >= 0; jhi -= kWY) {
+    const int jlo = jhi - kWY + 1 > 0 ? jhi - kWY + 1 : 0;
+    const int b = jhi - jlo + 1;
+    const int mlo = n - jlo - 1;
+    const double *Vb = E.wq + cur * kWY * n;
+    double *Vnext = E.wq + (cur ^ 1) * kWY * n;
+    // phase 1: w_t = V^T z_t (tasks t < k) and the Gram entries (tasks k .. k+b-2: v_c . v_l, l < c)
+    for (int task = grp; task < k + b - 1; task += kThreads / 4) {
+      const double *z = task < k ? Z + E.isrt[task] * n + jlo + 1 : Vb + (task - k + 1) * n;
+      double a[kWY] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = sub; i < mlo; i += 4) {
+        const double zi = z[i];
+#pragma unroll
+        for (int c = 0; c < kWY; ++c) a[c] += Vb[c * n + i] * zi;
       }
-      __syncthreads();
-      for (int ih = 0; ih < m; ih += 64) {
-        const int i = ih + lane;
-        if (i < m) {
-          const double vi = v[i];
-#pragma unroll 4
-          for (int t = wave; t < k; t += kThreads / 64) Z[E.isrt[t] * n + j + 1 + i] -= E.pp[t] * vi;
+#pragma unroll
+      for (int c = 0; c < kWY; ++c) {
+        a[c] += __shfl_xor(a[c], 1, 64);
+        a[c] += __shfl_xor(a[c], 2, 64);
+      }
+      if (sub == 0) {
+        if (task < k) {
+#pragma unroll
+          for (int c = 0; c < kWY; ++c) wbuf[task * kWY + c] = a[c];
+        } else {
+          const int cc = task - k + 1;       // G[l][cc] = v_l . v_cc for l < cc
+#pragma unroll
+          for (int l = 0; l < kWY; ++l) if (l < cc) G[l * kWY + cc] = a[l];
         }
       }
     }
-    if (j > 0)
-      for (int i = tid; i < m + 1; i += kThreads) vnext[i] = E.hv[int64_t(j - 1) * n + i];
+    if (tid < kWY) bet[tid] = (jlo + tid <= jhi) ? E.hv[int64_t(n) * n + jlo + tid] : 0.0;
+    __syncthreads();
+    // phase 2: T from the Gram entries and betas (every thread), z_t -= V (T w_t)
+    double T[kWY][kWY];
+#pragma unroll
+    for (int r = 0; r < kWY; ++r)
+#pragma unroll
+      for (int c = 0; c < kWY; ++c) T[r][c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < kWY; ++c) {
+      const double bc = c < b ? bet[c] : 0.0;
+#pragma unroll
+      for (int r = 0; r < kWY; ++r) {
+        if (r < c && c < b) {                    // T(r, c) = -beta_c sum_{l=r}^{c-1} T(r, l) G(l, c)
+          double acc = 0.0;
+#pragma unroll
+          for (int l = 0; l < kWY; ++l) if (l >= r && l < c) acc += T[r][l] * G[l * kWY + c];
+          T[r][c] = -bc * acc;
+        }
+      }
+      T[c][c] = bc;
+    }
+    for (int t = wave; t < k; t += kThreads / 64) {
+      double w[kWY], u[kWY];
+#pragma unroll
+      for (int c = 0; c < kWY; ++c) w[c] = wbuf[t * kWY + c];
+#pragma unroll
+      for (int r = 0; r < kWY; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kWY; ++c) acc += T[r][c] * w[c];
+        u[r] = acc;
+      }
+      double *z = Z + E.isrt[t] * n + jlo + 1;
+      for (int i = lane; i < mlo; i += 64) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kWY; ++c) acc += Vb[c * n + i] * u[c];
+        z[i] -= acc;
+      }
+    }
+    if (jlo > 0) stage(jlo - 1, Vnext);
     cur ^= 1;
     __syncthreads();
   }
