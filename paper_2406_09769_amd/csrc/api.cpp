@@ -132,32 +132,39 @@ int64_t box_static(const tn::Box &b) {
   return n;
 }
 
-// Ops whose output exceeds 2^21 elements (or a GEMM above 2^32 flops) run over the
-// whole chip; the rest of such a network runs in single-workgroup stretches between
-// them. Networks without such ops keep the one-pass interpreter.
+// A network with an op whose output exceeds 2^21 elements (or a GEMM above 2^32 flops)
+// runs op by op. In such a network every op with an output of at least 2^15 elements
+// (or a GEMM of at least 2^26 flops) runs over the whole chip, the rest in single-
+// workgroup stretches between them. Networks without such ops keep the one-pass
+// interpreter.
 void make_segments(DevPlan &dp) {
   constexpr int64_t kBigOut = int64_t(1) << 21, kBigFlops = int64_t(1) << 32;
-  std::vector<Seg> segs;
-  bool any = false;
+  constexpr int64_t kGridOut = int64_t(1) << 15, kGridFlops = int64_t(1) << 26;
   const auto &ops = dp.plan.ops;
+  auto out_of = [](const tn::Op &op) -> int64_t {
+    if (op.kind == tn::OP_GEMM) return int64_t(op.am.n) * op.bn.n;
+    if (op.kind == tn::OP_RESCALE) return box_static(op.bm) * box_static(op.bnb);
+    return 0;
+  };
+  bool any = false;
+  for (const tn::Op &op : ops) {
+    const int64_t out = out_of(op);
+    if (out >= kBigOut || (op.kind == tn::OP_GEMM && 2 * out * op.K >= kBigFlops)) any = true;
+  }
+  if (!any) return;
+  std::vector<Seg> segs;
   for (int64_t i = 0; i < int64_t(ops.size()); ++i) {
     const tn::Op &op = ops[size_t(i)];
+    const int64_t out = out_of(op);
     int kind = 0, blocks = 0;
-    if (op.kind == tn::OP_GEMM) {
-      const int64_t M = op.am.n, N = op.bn.n, out = M * N;
-      if (out >= kBigOut || 2 * out * op.K >= kBigFlops) {
-        kind = 1;
-        blocks = int(std::min<int64_t>(tn::kGridBlocks, ((M + 63) / 64) * ((N + 63) / 64)));
-      }
-    } else if (op.kind == tn::OP_RESCALE) {
-      const int64_t out = box_static(op.bm) * box_static(op.bnb);
-      if (out >= kBigOut) {
-        kind = 2;
-        blocks = int(std::min<int64_t>(tn::kGridBlocks, (out + 2047) / 2048));
-      }
+    if (op.kind == tn::OP_GEMM && (out >= kGridOut || 2 * out * op.K >= kGridFlops)) {
+      kind = 1;
+      blocks = int(std::min<int64_t>(tn::kGridBlocks, ((op.am.n + 63) / 64) * ((op.bn.n + 63) / 64)));
+    } else if (op.kind == tn::OP_RESCALE && out >= kGridOut) {
+      kind = 2;
+      blocks = int(std::min<int64_t>(tn::kGridBlocks, (out + 2047) / 2048));
     }
     if (kind) {
-      any = true;
       segs.push_back(Seg{kind, i, i + 1, std::max(blocks, 1)});
     } else if (!segs.empty() && segs.back().kind == 0) {
       segs.back().last = i + 1;
@@ -165,7 +172,7 @@ void make_segments(DevPlan &dp) {
       segs.push_back(Seg{0, i, i + 1, 1});
     }
   }
-  if (any) dp.segs = std::move(segs);
+  dp.segs = std::move(segs);
 }
 
 int get_plan(tn_net net, const std::vector<std::vector<int32_t>> &slices, int32_t chi, int32_t env,
