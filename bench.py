@@ -105,9 +105,27 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8, help="networks timed in the CPU oracle (0 = skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the runs of the other forms")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM block autotuner (built-in shapes)")
+    ap.add_argument("--cubic", type=int, default=0, metavar="CHI",
+                    help="only contract the 8x8x8 3D lattice (beta 0.2217, plane slices) once at max_rank CHI "
+                         "in FP64 and print its time (the chip-wide op path) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a buffer of MIB MiB once on the GPU (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.cubic > 0:
+        import torch
+        from paper_2406_09769_amd import inputs, tnapprox as T
+        net = inputs.ising_3d(8, 8, 8, 0.2217)
+        h = T.create_network(net)
+        stats = T.tn_plan_stats(h, net.slices, args.cubic, 1)
+        T.tn_contract_approx(h, net.slices, args.cubic, 1)          # plan, workspace, graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = T.tn_contract_approx(h, net.slices, args.cubic, 1)
+        dt = time.perf_counter() - t0
+        print(json.dumps({"workload": "ising3d_8x8x8_open_J1_h0 beta 0.2217 plane slices", "chi": args.cubic,
+                          "seconds": round(dt, 4), "kernel_s": round(r.seconds, 4), "log_abs": r.log_abs,
+                          "sign": r.sign, "gemm_flops": r.flops, "plan": stats}), flush=True)
+        return
     if args.copy_probe > 0:
         import torch
         n = args.copy_probe * (1 << 20) // 8

@@ -35,6 +35,7 @@ struct Seg {
   int kind;
   int64_t first, last;
   int blocks;
+  bool piped;        // kind 1: offsets fit the pipelined chip-wide kernel
 };
 
 struct DevPlan {
@@ -157,19 +158,21 @@ void make_segments(DevPlan &dp) {
     const tn::Op &op = ops[size_t(i)];
     const int64_t out = out_of(op);
     int kind = 0, blocks = 0;
+    bool piped = false;
     if (op.kind == tn::OP_GEMM && (out >= kGridOut || 2 * out * op.K >= kGridFlops)) {
       kind = 1;
       blocks = int(std::min<int64_t>(tn::kGridBlocks, ((op.am.n + 63) / 64) * ((op.bn.n + 63) / 64)));
+      piped = int64_t(op.am.n) + op.K <= int64_t(tn::kGridOffsetDoubles) && out < (int64_t(1) << 31);
     } else if (op.kind == tn::OP_RESCALE && out >= kGridOut) {
       kind = 2;
       blocks = int(std::min<int64_t>(tn::kGridBlocks, (out + 2047) / 2048));
     }
     if (kind) {
-      segs.push_back(Seg{kind, i, i + 1, std::max(blocks, 1)});
+      segs.push_back(Seg{kind, i, i + 1, std::max(blocks, 1), piped});
     } else if (!segs.empty() && segs.back().kind == 0) {
       segs.back().last = i + 1;
     } else {
-      segs.push_back(Seg{0, i, i + 1, 1});
+      segs.push_back(Seg{0, i, i + 1, 1, false});
     }
   }
   dp.segs = std::move(segs);
@@ -229,7 +232,7 @@ tn_options defaults() {
 int launch_segments(tn_net net, DevPlan *dp, const tn::KeepParams &kp, hipStream_t st) {
   for (const Seg &sg : dp->segs) {
     if (sg.kind == 0) HIP_TRY(tn::launch_interp_range(net->d_nd, sg.first, sg.last, kp, st));
-    else if (sg.kind == 1) HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, sg.blocks, kp.split, st));
+    else if (sg.kind == 1) HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, sg.blocks, kp.split, sg.piped, st));
     else HIP_TRY(tn::launch_rescale_grid(net->d_nd, sg.first, sg.blocks, net->d_part, st));
   }
   return TN_OK;

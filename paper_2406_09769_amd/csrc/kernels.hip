@@ -1593,11 +1593,11 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
 
 constexpr int kGridLds = 2 * kTK * kPitch + kKCache;   // gemm_tiles: two k-slices and both k caches
 constexpr int kGridPipedTiles = piped_stage_doubles(32, 128, 16);   // largest chip-wide piped configuration
-constexpr int kGridLdsAll = kGridLds > kGridPipedTiles + 1216 ? kGridLds : kGridPipedTiles + 1216;
+constexpr int kGridLdsAll = kGridLds > kGridPipedTiles + kGridOffsetDoubles ? kGridLds : kGridPipedTiles + kGridOffsetDoubles;
 
 // FP64 chip-wide GEMM through the pipelined path: k and row offsets cached in LDS,
 // each workgroup a contiguous range of output blocks. False if the caches do not fit.
-__device__ bool gemm_grid_piped(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
+__device__ __forceinline__ bool gemm_grid_piped(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
                                 double *__restrict__ C, const int32_t *__restrict__ tab, double *lds,
                                 NetScalars *sc) {
   const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
@@ -1636,6 +1636,20 @@ __device__ bool gemm_grid_piped(const Op &op, const double *__restrict__ A, cons
     gemm_piped<64, 64, 16, 2, 2, true>(op, A, B, C, lds, M, N, K, kA, kB, rA, nullptr, rC, nullptr, tab, b0, b1);
   }
   return true;
+}
+
+// FP64 chip-wide GEMM whose row and k offsets fit LDS (checked on the host from the
+// static shapes): a kernel of its own, so its register budget is the pipelined path's
+// alone and two workgroups share a CU.
+__global__ __launch_bounds__(kThreads, 2) void gemm_grid_piped_kernel(const NetDev *__restrict__ ndp, int64_t i) {
+  __shared__ double lds[kGridLdsAll];
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
+  const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
+  gemm_grid_piped(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc);
 }
 
 __global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__restrict__ ndp, int64_t i, int split) {
@@ -1713,8 +1727,11 @@ hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, hipStream_t stream) {
-  hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i, split);
+hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, bool piped, hipStream_t stream) {
+  if (split == 0 && piped)
+    hipLaunchKernelGGL(gemm_grid_piped_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);
+  else
+    hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i, split);
   return hipGetLastError();
 }
 

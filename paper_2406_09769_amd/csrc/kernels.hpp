@@ -53,7 +53,10 @@ hipError_t launch_interp(const NetDev *nets_dev, int n_nets, const KeepParams &k
 constexpr int kGridBlocks = 2048;
 hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last, const KeepParams &kp,
                                hipStream_t stream);
-hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, hipStream_t stream);
+// piped: the op's static rows + k fit kGridOffsetDoubles doubles of int32 offset pairs
+// and its static output is below 2^31 elements (FP64 runs the pipelined kernel then).
+constexpr int kGridOffsetDoubles = 1216;
+hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, bool piped, hipStream_t stream);
 hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, double *partial, hipStream_t stream);
 
 }  // namespace tn
