@@ -289,12 +289,12 @@ __device__ void gemm_piped(const Op &op, const double *__restrict__ A, const dou
 // (max |x| of the op's valid box brought into [1/2, 1)), every value is split into
 // three 16-bit floats, each the rounding of what the previous ones leave, and the
 // product is the sum of the six part products of order <= 2 (hh, hm, mh, hl, lh, mm)
-// on the 16-bit matrix cores with FP32 accumulation. BF16 (8-bit significand, FP32
-// range): x = h + m + l, one accumulator. FP16 (11-bit significand, narrow range):
-// the remainders are scaled up before rounding, x = h + 2^-11 m + 2^-22 l, so the
-// parts stay normal, and the products of each order get their own accumulator,
-// combined as acc0 + 2^-11 acc1 + 2^-22 acc2. The result is scaled back exactly and
-// stored in FP64.
+// on the 16-bit matrix cores, accumulated in FP32 over each 16-deep k chunk and in
+// FP64 across chunks. BF16 (8-bit significand, FP32 range): x = h + m + l, one
+// accumulator. FP16 (11-bit significand, narrow range): the remainders are scaled up
+// before rounding, x = h + 2^-11 m + 2^-22 l, so the parts stay normal, and the
+// products of each order get their own accumulator, combined as
+// acc0 + 2^-11 acc1 + 2^-22 acc2. The result is scaled back exactly and stored in FP64.
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
@@ -416,6 +416,13 @@ __device__ void gemm_split(const Op &op, const double *__restrict__ A, const dou
 #pragma unroll
       for (int b = 0; b < TN; ++b) acc[o][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
   constexpr int O1 = NACC > 1 ? 1 : 0, O2 = NACC > 1 ? 2 : 0;
+  double acc64[TM][TN][4];                         // FP64 sum of the 16-deep FP32 chunk sums
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
   if (steps > 0) load(0);
   for (int s = 0; s < steps; ++s) {
     const int buf = s & 1;
@@ -451,6 +458,14 @@ __device__ void gemm_split(const Op &op, const double *__restrict__ A, const dou
           acc[O1][a][b] = mfma16<SPLIT>(am[a], bh[b], acc[O1][a][b]);
           acc[O1][a][b] = mfma16<SPLIT>(ah[a], bm[b], acc[O1][a][b]);
           acc[0][a][b] = mfma16<SPLIT>(ah[a], bh[b], acc[0][a][b]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double v = double(acc[0][a][b][r]);
+            if (NACC > 1) v += double(acc[O1][a][b][r]) * 0x1p-11 + double(acc[O2][a][b][r]) * 0x1p-22;
+            acc64[a][b][r] += v;
+          }
+#pragma unroll
+          for (int o = 0; o < NACC; ++o) acc[o][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
         }
     }
     if (ch == nch - 1) {
@@ -463,12 +478,9 @@ __device__ void gemm_split(const Op &op, const double *__restrict__ A, const dou
           for (int r = 0; r < 4; ++r) {
             const int row = m0 + wm * TM * 16 + a * 16 + 4 * (lane >> 4) + r;   // D: lane l, reg r = row 4(l/16) + r
             const int col = n0 + wn * TN * 16 + b * 16 + (lane & 15);
-            double v = double(acc[0][a][b][r]);
-            if (NACC > 1) v += double(acc[O1][a][b][r]) * 0x1p-11 + double(acc[O2][a][b][r]) * 0x1p-22;
-            if (row < M && col < N) C[int64_t(rC[row]) + cC[col]] = v * unscale;
+            if (row < M && col < N) C[int64_t(rC[row]) + cC[col]] = acc64[a][b][r] * unscale;
+            acc64[a][b][r] = 0.0;
           }
-#pragma unroll
-          for (int o = 0; o < NACC; ++o) acc[o][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
         }
     }
   }
