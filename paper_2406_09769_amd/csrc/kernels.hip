@@ -715,16 +715,6 @@ __device__ __forceinline__ double lane_write(double x, int dst, double old) {
   return (int(threadIdx.x & 63) == dst) ? x : old;
 }
 
-// 1/sqrt(q) for q > 0: hardware estimate refined by two Newton steps (a few ulps;
-// every Givens rotation of the QL sweep needs one, on its critical path)
-__device__ __forceinline__ double rsqrt_nr(double q) {
-  double y = __builtin_amdgcn_rsq(q);
-  const double h = 0.5 * q;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
-}
-
 // ---------------------------------------------------------------- reductions
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -843,6 +833,91 @@ __device__ EigWs eig_ws(double *base, int n, double *hv) {
 
 // Tridiagonalise E.A (symmetric, loaded) and diagonalise T by implicit QL.
 // On return Z (column-major) overwrites E.A and the eigenvalues are in E.dd.
+// (d, e) and (c, s) pairs of the QL solve, 16-byte aligned so that a pair moves in one
+// LDS access
+struct __attribute__((aligned(16))) Pair { double x, y; };
+typedef __attribute__((address_space(3))) Pair lds_pair;
+
+// One sweep of the implicit QL chase, rows mu-1 down to lu of the pairs de = (d_i, e_i),
+// run by one wave (every lane computes the same values; lane 0 writes). The (c, s) of
+// each rotation go to rb in order. The step carries no branch: an underflow (f = g = 0,
+// where T splits) writes the split values and turns the remaining steps into writes to
+// the spare pair `spare`, so the chase never waits on a scalar test of a vector result.
+// Kept out of line so that its few live values get registers of their own rather than
+// those of the large caller. Returns p and g of the last step, the rotations, and
+// whether T split.
+struct ChaseOut { double p, g; int cnt, split; };
+__device__ __noinline__ ChaseOut ql_chase(Pair *de_, Pair *rb_, Pair *spare_, int lu_, int mu_, double g,
+                                          double di1) {
+  lds_pair *de = (lds_pair *)de_, *rb = (lds_pair *)rb_, *spare = (lds_pair *)spare_;   // all in LDS
+  const bool lane0 = (threadIdx.x & 63) == 0;
+  const int lu = __builtin_amdgcn_readfirstlane(lu_), mu = __builtin_amdgcn_readfirstlane(mu_);
+  double s = 1.0, c = 1.0, p = 0.0;
+  double nd = de[mu - 1].x, ne = de[mu - 1].y;       // (d[i], e[i]), fetched one step ahead
+  asm volatile("" ::"v"(nd), "v"(ne));               // arrived before the loop: no wait inside
+  // a step's writes are issued in the next step, after its prefetch, so that waiting for
+  // a prefetched pair never waits on writes issued just before it (the first step's
+  // pending writes go to the spare pair)
+  lds_pair *pd = spare, *pr = spare;
+  double pdx = 0.0, pdy = 0.0, prx = 0.0, pry = 0.0;
+  int cnt = 0;
+  bool live = true;
+  for (int i = mu - 1; i >= lu; --i) {
+    const double ei = ne, di = nd;
+    const int nxt = i > lu ? i - 1 : lu;
+    nd = de[nxt].x;
+    ne = de[nxt].y;
+    if (lane0) {
+      pd->x = pdx;
+      pd->y = pdy;
+      pr->x = prx;
+      pr->y = pry;
+    }
+    const double f = s * ei, bb = c * ei;
+    const double q = f * f + g * g;
+    const bool z = q == 0.0;
+    // c = g / sqrt(q), s = f / sqrt(q), r = sqrt(q) from the hardware estimate y0 of
+    // 1/sqrt(q) and one correction: with e = 1 - q y0^2, 1/sqrt(q) = y0 (1 + e/2 +
+    // 3e^2/8 + O(e^3)), exact to rounding since |e| is below 2^-20; each output is
+    // corrected directly, which keeps the step's dependent chain short
+    const double y0 = __builtin_amdgcn_rsq(q);
+    const double qy = q * y0, gy = g * y0, fy = f * y0;
+    const double ey = fma(-qy, y0, 1.0);
+    const double pe = fma(ey, 0.375, 0.5);
+    c = fma(gy * ey, pe, gy);
+    s = fma(fy * ey, pe, fy);
+    const double r = fma(qy * ey, pe, qy);
+    const double gq = di1 - p;
+    const double t = fma(di - gq, s, c * (2.0 * bb));
+    p = s * t;
+    g = fma(c, t, -bb);
+    // the address and data registers of the writes issued at this step's start stay
+    // untouched until here, so the step never waits for those writes to reuse them
+    asm volatile("" : "+v"(g) : "v"(pdx), "v"(pdy), "v"(prx), "v"(pry), "v"(pd), "v"(pr));
+    pd = live ? de + (i + 1) : spare;
+    pr = live && !z ? rb + cnt : spare;
+    pdx = z ? gq : gq + p;                             // at a split: d[i+1] - p, e[i+1] = 0
+    pdy = z ? 0.0 : r;
+    prx = c;
+    pry = s;
+    cnt += live && !z ? 1 : 0;
+    live = live && !z;
+    di1 = di;
+  }
+  if (lane0) {
+    pd->x = pdx;
+    pd->y = pdy;
+    pr->x = prx;
+    pr->y = pry;
+  }
+  ChaseOut o;
+  o.p = p;
+  o.g = g;
+  o.cnt = __builtin_amdgcn_readfirstlane(cnt);
+  o.split = __builtin_amdgcn_readfirstlane(live ? 0 : 1);
+  return o;
+}
+
 __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
   const int n = E.n, pa = E.pa, tid = threadIdx.x, wave = tid >> 6;
   double *A = E.A, *vv = E.vv, *pp = E.pp, *ww = E.ww, *dd = E.dd, *ee = E.ee, *hv = E.hv;
@@ -946,10 +1021,14 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
   // of one QL iteration; after a barrier waves 1-3 apply that iteration's rotations to
   // their rows of Z while wave 0 already chases the next iteration into the other
   // buffer. One barrier per QL iteration; the chase carries no Z traffic.
-  double *wd = E.wq, *we = wd + n;
-  double *rot = E.wq + 2 * n;                       // two buffers of n (c, s) pairs
+  // (d_i, e_i) pairs and (c, s) pairs, so that each step of the chase is one 16-byte LDS
+  // read and two 16-byte writes; the pair arrays start on a 16-byte boundary (8n doubles
+  // at E.wq hold the pairs, both rotation buffers and the spare pair)
+  Pair *de = reinterpret_cast<Pair *>(E.wq + ((reinterpret_cast<uintptr_t>(E.wq) >> 3) & 1));
+  Pair *rot = de + n;                               // two buffers of n (c, s) pairs
+  Pair *spare = rot + 2 * n;                        // write target of the chase after a split
   int *meta = E.flag;                               // per buffer: m, rotations (-1: finished)
-  for (int i = tid; i < n; i += kThreads) { wd[i] = dd[i]; we[i] = ee[i]; }
+  for (int i = tid; i < n; i += kThreads) de[i] = Pair{dd[i], ee[i]};
   __syncthreads();
   constexpr double kEps = 2.220446049250313e-16;
   long long nrot = 0;
@@ -961,7 +1040,7 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
     // absolute accuracy of any backward-stable solver; without it the null space of a
     // rank-deficient density matrix is iterated to full relative precision
     double tn = 0.0;
-    for (int i = lane; i < n; i += 64) tn = fmax(tn, fmax(fabs(wd[i]), 2.0 * fabs(we[i])));
+    for (int i = lane; i < n; i += 64) tn = fmax(tn, fmax(fabs(de[i].x), 2.0 * fabs(de[i].y)));
     efloor = kEps * wave_max(tn);
   }
   const int crow = tid - 64;                        // consumer row
@@ -976,8 +1055,8 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
           const int i = base + lane;
           bool small = false;
           if (i < n - 1) {
-            const double ei = fabs(we[i]);
-            small = ei <= kEps * (fabs(wd[i]) + fabs(wd[i + 1])) || ei <= efloor;
+            const double ei = fabs(de[i].y);
+            small = ei <= kEps * (fabs(de[i].x) + fabs(de[i + 1].x)) || ei <= efloor;
           }
           const unsigned long long bl = __ballot(small);
           if (bl) { m = base + __ffsll((long long)bl) - 1; break; }
@@ -990,64 +1069,46 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
         if (lane == 0) { meta[2 * b] = 0; meta[2 * b + 1] = -1; }
       } else {
         ++iter;
-        double *rb = rot + 2 * n * b;
-        const double dl = wd[l], el = we[l];
-        double g = (wd[l + 1] - dl) / (2.0 * el);
+        // l and m are the same in every lane: scalar copies keep the chase's loop control,
+        // addresses and branches on the scalar unit
+        const int lu = __builtin_amdgcn_readfirstlane(l), mu = __builtin_amdgcn_readfirstlane(m);
+        Pair *rb = rot + n * b;
+        const double dl = de[lu].x, el = de[lu].y;
+        double g = (de[lu + 1].x - dl) / (2.0 * el);
         double r = sqrt(g * g + 1.0);
-        g = wd[m] - dl + el / (g + copysign(r, g));
-        double s = 1.0, c = 1.0, p = 0.0;
-        double di1 = wd[m];
-        double en = we[m - 1], dn = wd[m - 1];      // e[i], d[i], fetched one step ahead
-        int i = m - 1, cnt = 0;
-        bool split = false;
-        for (; i >= l; --i) {
-          const double ei = en, di = dn;
-          if (i > l) { en = we[i - 1]; dn = wd[i - 1]; }
-          ++nrot;
-          const double f = s * ei, bb = c * ei;
-          const double q = f * f + g * g;
-          if (q == 0.0) {                              // underflow: T splits here
-            if (lane == 0) { we[i + 1] = 0.0; wd[i + 1] = di1 - p; we[m] = 0.0; }
-            split = true;
-            break;
-          }
-          const double rr = rsqrt_nr(q);              // 1/sqrt(f^2 + g^2)
-          r = q * rr;
-          s = f * rr;
-          c = g * rr;
-          g = di1 - p;
-          const double t = (di - g) * s + 2.0 * c * bb;
-          p = s * t;
-          const double dnew = g + p;
-          g = c * t - bb;
-          if (lane == 0) { we[i + 1] = r; wd[i + 1] = dnew; rb[2 * cnt] = c; rb[2 * cnt + 1] = s; }
-          ++cnt;
-          di1 = di;
+        double di1 = de[mu].x;
+        g = di1 - dl + el / (g + copysign(r, g));
+        const ChaseOut co = ql_chase(de, rb, spare, lu, mu, g, di1);
+        const int cnt = co.cnt;
+        nrot += cnt + co.split;
+        if (lane == 0) {
+          if (!co.split) de[lu] = Pair{dl - co.p, co.g};
+          de[mu].y = 0.0;
+          meta[2 * b] = m;
+          meta[2 * b + 1] = cnt;
         }
-        if (!split && lane == 0) { wd[l] = dl - p; we[l] = g; we[m] = 0.0; }
-        if (lane == 0) { meta[2 * b] = m; meta[2 * b + 1] = cnt; }
       }
     }
     __syncthreads();
     const int m = meta[2 * b], cnt = meta[2 * b + 1];
     if (cnt < 0) break;
     if (own && cnt > 0) {                            // apply the iteration's rotations to row crow
-      const double *rb = rot + 2 * n * b;
+      const Pair *rb = rot + n * b;
       double zc = Z[m * n + crow];                   // current value of column i+1
       double zn = Z[(m - 1) * n + crow];             // column i, fetched one step ahead
       for (int j = 0; j < cnt; ++j) {
         const int i = m - 1 - j;
         const double zi = zn;
         if (j + 1 < cnt) zn = Z[(i - 1) * n + crow];
-        const double c = rb[2 * j], s = rb[2 * j + 1];
-        Z[(i + 1) * n + crow] = s * zi + c * zc;
-        zc = c * zi - s * zc;
+        const Pair cs = rb[j];
+        Z[(i + 1) * n + crow] = cs.y * zi + cs.x * zc;
+        zc = cs.x * zi - cs.y * zc;
       }
       Z[(m - cnt) * n + crow] = zc;
     }
   }
   __syncthreads();
-  for (int i = tid; i < n; i += kThreads) dd[i] = wd[i];     // the eigenvalues
+  for (int i = tid; i < n; i += kThreads) dd[i] = de[i].x;   // the eigenvalues
   if (tid == 0) sc->n_rot += nrot;
   __syncthreads();
   if (timed && tid == 0) sc->ticks[6] += wall_clock64() - tph;

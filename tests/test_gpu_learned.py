@@ -109,7 +109,7 @@ def test_learned_solve_matches_oracle_rule(T):
     m.set(w.astype(np.float32))
     st = dm.Stats()
     dm.contract_approx(inputs.ising_2d(16, 16, 0.44), 16, 1, stats=st, harvest=True)
-    agree = total = acc = 0
+    agree = total = acc = rank_diff = 0
     for L, _ in st.harvest:
         n = L.shape[0]
         if n < 16:
@@ -127,14 +127,21 @@ def test_learned_solve_matches_oracle_rule(T):
             Ug = U[:, :k]
             assert np.allclose(Ug.T @ Ug, np.eye(k), atol=1e-12)
             # what the kept subspace captures of L equals the exact one's, up to the
-            # directions the rule may leave out (weight <= 1e-11 theta_1 in total)
+            # directions the rule may leave out (weight <= TAIL_REL theta_1 in total)
             cap_g = np.trace(Ug.T @ Ls @ Ug)
             cap_e = we[:ke].sum()
-            assert abs(cap_g - cap_e) <= 2e-11 * n * we[0]
-            if ok:
-                assert k == ko
-    print(f"learned solves: device accepted {acc}/{total}, decisions agree with the rule on {agree}/{total}",
-          flush=True)
+            assert abs(cap_g - cap_e) <= 2 * mlp.TAIL_REL * n * we[0]
+            if ok and k != ko:
+                # both ranks satisfy the rule when every eigenvalue between them is one the
+                # cutoff form may leave out (below TAIL_REL theta_1): the Ritz value of such a
+                # direction depends on how much of it the subspace happens to hold
+                lo, hi = min(k, ko), max(k, ko)
+                print(f"rank differs: n {n} device {k} rule {ko} exact {ke}, theta/theta1 between "
+                      f"{np.array2string(we[lo:hi] / we[0], precision=2)}", flush=True)
+                assert we[lo:hi].max() <= mlp.TAIL_REL * we[0]
+                rank_diff += 1
+    print(f"learned solves: device accepted {acc}/{total}, decisions agree with the rule on {agree}/{total}, "
+          f"kept ranks differ below TAIL_REL on {rank_diff}", flush=True)
     assert acc > 0.5 * total
     assert agree >= 0.95 * total
 
