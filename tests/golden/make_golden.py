@@ -6,7 +6,10 @@ Calls only oracle/ (and the seeded input generators). Usage:
     python tests/golden/make_golden.py w5   # 32 random 3-SAT #CSP formulas, n 150, m 450, chi 32
     python tests/golden/make_golden.py w4spread  # how far FP64 fixes each W4 result (see spread())
     python tests/golden/make_golden.py w5small   # 8 random 3-SAT formulas, n 50, m 150, chi 32
+    python tests/golden/make_golden.py w5smallspread  # how far FP64 fixes each of those results
     python tests/golden/make_golden.py w3   # 8x8x8 3D Ising at the 3 betas, chi 16, plane slices
+    python tests/golden/make_golden.py w3spread 0.25 [--hows=evr,perturbed_0,perturbed13_0]
+                                            # how far FP64 fixes the W3 result at these betas
 """
 import json
 import math
@@ -59,32 +62,96 @@ def w3(out_path):
                "rows": rows}, open(out_path, "w"), indent=1)
 
 
-def _spread_one(i):
-    """Oracle result of W4 instance i under three other equally valid FP64 evaluations:
-    LAPACK's MRRR driver (evr) in place of the default divide-and-conquer one, and the
-    default solver on the network with every tensor entry scaled by (1 + 1e-15 z),
-    z standard normal (two seeds). Returns the largest |dlnZ|/N from the stored value."""
+def _w3_spread_one(args):
+    """One alternative FP64 evaluation of a W3 lattice: LAPACK's MRRR driver ("evr"), or the
+    default solver on inputs scaled by (1 + a z), z standard normal with the given seed,
+    a = 1e-15 ("perturbed_<seed>") or a = 1e-13 ("perturbed13_<seed>", the relative rounding
+    bound of an FP64 sum of about 10^3 terms, the depth of this lattice's contractions)."""
     import copy
     import numpy as np
     import scipy.linalg as sl
-    gold = json.load(open(os.path.join(HERE, "w4_oracle.json")))["rows"][i]
-    net = inputs.rrg_batch(i + 1)[i]
+    beta, how = args
+    net = inputs.ising_3d(8, 8, 8, beta)
+    if how == "evr":
+        dm.EIGH = lambda L: sl.eigh(L, driver="evr")
+    else:
+        amp = 1e-13 if how.startswith("perturbed13_") else 1e-15
+        rng = np.random.default_rng(int(how.rsplit("_", 1)[1]))
+        net = copy.deepcopy(net)
+        net.tensors = [t * (1.0 + amp * rng.standard_normal(t.shape)) for t in net.tensors]
+    v = dm.contract_approx(net, 16, 1)[0]
+    print(json.dumps({"beta": beta, "how": how, "log_abs": v}), flush=True)
+    return beta, how, v
+
+
+def w3spread(out_path, betas, hows):
+    """Deviation per site of each alternative evaluation from the stored oracle value; rows
+    already in out_path are kept and extended."""
+    gold = {r["beta"]: r for r in json.load(open(os.path.join(HERE, "w3_oracle.json")))["rows"]}
+    old = {r["beta"]: r for r in json.load(open(out_path))["rows"]} if os.path.exists(out_path) else {}
+    jobs = [(b, h) for b in betas for h in hows]
+    if len(jobs) == 1:
+        res = [_w3_spread_one(jobs[0])]
+    else:
+        with Pool(2) as pool:
+            res = pool.map(_w3_spread_one, jobs)
+    for b in betas:
+        row = {k: v for k, v in old.get(b, {"beta": b}).items() if k != "spread"}
+        row.update({h: abs(v - gold[b]["log_abs"]) / 512 for bb, h, v in res if bb == b})
+        old[b] = {"beta": b, "spread": max(v for k, v in row.items() if k != "beta"),
+                  **{k: v for k, v in row.items() if k != "beta"}}
+    json.dump({"workload": "8x8x8 lattice of w3_oracle.json, chi 16",
+               "what": "largest |dlnZ|/N between the stored oracle value and the oracle under an "
+                       "alternative LAPACK eigensolver (evr), or relative input noise of 1e-15 "
+                       "(perturbed_s) or 1e-13 (perturbed13_s, the rounding bound of an FP64 sum "
+                       "of about 10^3 terms)",
+               "rows": [old[b] for b in sorted(old)]}, open(out_path, "w"), indent=1)
+
+
+def _spread_one(i, kind="w4"):
+    """Oracle result of instance i (W4 graphs, or the small #CSP formulas for kind "w5small")
+    under three other equally valid FP64 evaluations: LAPACK's MRRR driver (evr) in place of
+    the default divide-and-conquer one, and the default solver on the network with every
+    tensor entry scaled by (1 + 1e-15 z), z standard normal (two seeds). Returns the largest
+    |dlnZ|/N from the stored value."""
+    import copy
+    import numpy as np
+    import scipy.linalg as sl
+    if kind == "w4":
+        gold = json.load(open(os.path.join(HERE, "w4_oracle.json")))["rows"][i]
+        net, chi = inputs.rrg_batch(i + 1)[i], 64
+    else:
+        gold = json.load(open(os.path.join(HERE, "w5_small_oracle.json")))["rows"][i]
+        net, chi = inputs.csp_batch(i + 1, n_vars=50)[i], 32
     assert net.name == gold["name"]
     vals = {}
     dm.EIGH = lambda L: sl.eigh(L, driver="evr")
     try:
-        vals["evr"] = dm.contract_approx(net, 64, 1)[0]
+        vals["evr"] = dm.contract_approx(net, chi, 1)[0]
     finally:
         dm.EIGH = np.linalg.eigh
     for seed in (0, 1):
         rng = np.random.default_rng(seed)
         net2 = copy.deepcopy(net)
         net2.tensors = [t * (1.0 + 1e-15 * rng.standard_normal(t.shape)) for t in net.tensors]
-        vals[f"perturbed_{seed}"] = dm.contract_approx(net2, 64, 1)[0]
+        vals[f"perturbed_{seed}"] = dm.contract_approx(net2, chi, 1)[0]
     dev = {k: abs(v - gold["log_abs"]) / net.n_sites for k, v in vals.items()}
     row = {"index": i, "name": net.name, "spread": max(dev.values()), **dev}
     print(json.dumps(row), flush=True)
     return row
+
+
+def _spread_w5small(i):
+    return _spread_one(i, "w5small")
+
+
+def spread_w5small(out_path, workers=4):
+    with Pool(workers) as pool:
+        rows = sorted(pool.map(_spread_w5small, range(8)), key=lambda r: r["index"])
+    json.dump({"workload": "the 8 formulas of w5_small_oracle.json",
+               "what": "largest |dlnZ|/N between the stored oracle value and the oracle under an "
+                       "alternative LAPACK eigensolver (evr) or 1e-15 relative input noise (2 seeds)",
+               "rows": rows}, open(out_path, "w"), indent=1)
 
 
 def spread(out_path, workers=4):
@@ -139,5 +206,12 @@ if __name__ == "__main__":
         spread(os.path.join(HERE, "w4_spread.json"))
     elif which == "w3":
         w3(os.path.join(HERE, "w3_oracle.json"))
+    elif which == "w3spread":
+        args = [a for a in sys.argv[2:] if not a.startswith("--hows=")]
+        hows = [a[7:].split(",") for a in sys.argv[2:] if a.startswith("--hows=")]
+        w3spread(os.path.join(HERE, "w3_spread.json"), [float(x) for x in args],
+                 hows[0] if hows else ["evr", "perturbed_0"])
     elif which == "w5small":
         batch("w5small", 8, 32, os.path.join(HERE, "w5_small_oracle.json"))
+    elif which == "w5smallspread":
+        spread_w5small(os.path.join(HERE, "w5_small_spread.json"))

@@ -8,7 +8,10 @@
   other equally valid FP64 evaluations (another LAPACK eigensolver; 1e-15 relative
   input noise, two seeds). The bound per graph is max(1e-10, 10 x that spread); the
   graphs whose spread is below 1e-11 must meet 1e-10 outright.
-* 8 random 3-SAT model counts (n 50, m 150, chi 32) as #CSP networks. (The 150-
+* 8 random 3-SAT model counts (n 50, m 150, chi 32) as #CSP networks. Their 0/1
+  tensors make the spectra at the chi cut degenerate, so FP64 fixes these counts even
+  less: the oracle moves by up to 1e-5 per variable under the evaluations above
+  (tests/golden/w5_small_spread.json); the same per-formula bound applies. (The 150-
   variable formulas take about three minutes each on one workgroup: their values
   are stored in w5_oracle.json, but no test runs them.)
 
@@ -61,15 +64,20 @@ def test_rrg_batch_of_64_matches_oracle(T):
 
 def test_csp_batch_matches_oracle(T):
     gold = json.load(open(os.path.join(GOLD, "w5_small_oracle.json")))["rows"]
+    spread = {r["name"]: r["spread"]
+              for r in json.load(open(os.path.join(GOLD, "w5_small_spread.json")))["rows"]}
     nets = inputs.csp_batch(8, n_vars=50)
     print("3-SAT #CSP batch: 8 formulas, n 50, m 150, chi 32, one launch", flush=True)
     rs = _run(T, nets, 32)
-    errs = []
+    ratios = []
     for net, g, r in zip(nets, gold, rs):
         assert net.name == g["name"]
         assert r.sign == g["sign"], net.name
         assert r.n_eig == g["n_eig"]
-        errs.append(abs(r.log_abs - g["log_abs"]) / net.n_sites)
-    print(f"kernel {rs[0].seconds:.2f} s, {sum(r.n_eig for r in rs)} eigensolves, worst |dlnZ|/N {max(errs):.2e}",
-          flush=True)
-    assert max(errs) <= BOUND
+        err = abs(r.log_abs - g["log_abs"]) / net.n_sites
+        sp = spread[net.name]
+        print(f"  {net.name}: |dlnZ|/N {err:.2e}, oracle spread {sp:.2e}", flush=True)
+        assert err <= max(BOUND, 10 * sp), (net.name, err, sp)
+        ratios.append(err / max(BOUND, 10 * sp))
+    print(f"kernel {rs[0].seconds:.2f} s, {sum(r.n_eig for r in rs)} eigensolves, worst error / bound "
+          f"{max(ratios):.2f}", flush=True)
