@@ -702,19 +702,6 @@ __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double
   return true;
 }
 
-// ---------------------------------------------------------------- lane access
-
-// value of v in lane `src` (src wave-uniform), as a wave-uniform scalar
-__device__ __forceinline__ double lane_read(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
-// `old` with lane `dst` replaced by the wave-uniform value x (a per-lane select)
-__device__ __forceinline__ double lane_write(double x, int dst, double old) {
-  return (int(threadIdx.x & 63) == dst) ? x : old;
-}
-
 // ---------------------------------------------------------------- reductions
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -1603,11 +1590,19 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
 
 // Stage op i of a network in LDS with every Box's slot ids replaced by the runtime
 // extents they hold (the whole workgroup takes part).
-__device__ void stage_op(const NetDev &nd, int64_t i, Op &s_op) {
+constexpr int kOpWords = int(sizeof(Op) / 4);
+static_assert(kOpWords <= kThreads, "Op must be staged by one pass of the workgroup");
+
+// word tid of op i of the network (threads below kOpWords)
+__device__ __forceinline__ int32_t op_word(const NetDev &nd, int64_t i) {
+  return threadIdx.x < kOpWords ? reinterpret_cast<const int32_t *>(nd.ops + i)[threadIdx.x] : 0;
+}
+
+// Stage an op from its words (one per thread) into LDS, then replace its Box slot ids
+// by the runtime extents those slots hold.
+__device__ void stage_op_words(const NetDev &nd, int32_t w, Op &s_op) {
   const int tid = threadIdx.x;
-  constexpr int kOpWords = int(sizeof(Op) / 4);
-  static_assert(kOpWords <= kThreads, "Op must be staged by one pass of the workgroup");
-  if (tid < kOpWords) reinterpret_cast<int32_t *>(&s_op)[tid] = reinterpret_cast<const int32_t *>(nd.ops + i)[tid];
+  if (tid < kOpWords) reinterpret_cast<int32_t *>(&s_op)[tid] = w;
   __syncthreads();
   if (tid < 3 * kMaxDyn) {
     Box *bx = tid < kMaxDyn ? &s_op.bm : (tid < 2 * kMaxDyn ? &s_op.bnb : &s_op.bk_);
@@ -1617,6 +1612,8 @@ __device__ void stage_op(const NetDev &nd, int64_t i, Op &s_op) {
   __syncthreads();
 }
 
+__device__ void stage_op(const NetDev &nd, int64_t i, Op &s_op) { stage_op_words(nd, op_word(nd, i), s_op); }
+
 // One workgroup walks ops [first, last) of its network (last < 0: to the end).
 __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restrict__ nets, KeepParams kp,
                                                           int64_t first, int64_t last) {
@@ -1625,8 +1622,12 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
   const NetDev nd = nets[blockIdx.x];
   const int tid = threadIdx.x;
   const int64_t end = last < 0 ? nd.n_ops : last;
+  // the next op's words are loaded while the current op runs: the op arrays are read once
+  // per launch, so each descriptor would otherwise cost a full memory round trip
+  int32_t w = first < end ? op_word(nd, first) : 0;
   for (int64_t i = first; i < end; ++i) {
-    stage_op(nd, i, s_op);
+    stage_op_words(nd, w, s_op);
+    if (i + 1 < end) w = op_word(nd, i + 1);
     const Op &op = s_op;
     const int kind = op.kind;
     const long long t0 = wall_clock64();
