@@ -1619,8 +1619,17 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
                                                           int64_t first, int64_t last) {
   __shared__ double lds[kLdsDoubles];
   __shared__ Op s_op;                 // the current op, Box slot ids replaced by extents
-  const NetDev nd = nets[blockIdx.x];
+  __shared__ NetScalars s_sc;         // the network's scalars while the workgroup runs
+  constexpr int kScWords = int(sizeof(NetScalars) / 8);
+  static_assert(kScWords <= kThreads, "NetScalars is copied by one pass of the workgroup");
+  NetDev nd = nets[blockIdx.x];
+  NetScalars *const g_sc = nd.sc;
   const int tid = threadIdx.x;
+  // counters and sums are updated by one thread after most ops; kept in LDS, no update
+  // waits on a memory round trip before the next barrier
+  if (tid < kScWords) reinterpret_cast<long long *>(&s_sc)[tid] = reinterpret_cast<const long long *>(g_sc)[tid];
+  __syncthreads();
+  nd.sc = &s_sc;
   const int64_t end = last < 0 ? nd.n_ops : last;
   // the next op's words are loaded while the current op runs: the op arrays are read once
   // per launch, so each descriptor would otherwise cost a full memory round trip
@@ -1657,6 +1666,8 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
     __syncthreads();
     if (tid == 0) nd.sc->ticks[kind & 7] += wall_clock64() - t0;
   }
+  __syncthreads();
+  if (tid < kScWords) reinterpret_cast<long long *>(g_sc)[tid] = reinterpret_cast<const long long *>(&s_sc)[tid];
 }
 
 // ---------------------------------------------------------------- grid-wide ops
