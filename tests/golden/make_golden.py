@@ -66,7 +66,9 @@ def _w3_spread_one(args):
     """One alternative FP64 evaluation of a W3 lattice: LAPACK's MRRR driver ("evr"), or the
     default solver on inputs scaled by (1 + a z), z standard normal with the given seed,
     a = 1e-15 ("perturbed_<seed>") or a = 1e-13 ("perturbed13_<seed>", the relative rounding
-    bound of an FP64 sum of about 10^3 terms, the depth of this lattice's contractions)."""
+    bound of an FP64 sum of about 10^3 terms, the depth of this lattice's contractions), or
+    the default solver with every pairwise contraction result scaled by (1 + 1e-15 z)
+    ("gemmnoise_<seed>")."""
     import copy
     import numpy as np
     import scipy.linalg as sl
@@ -74,6 +76,13 @@ def _w3_spread_one(args):
     net = inputs.ising_3d(8, 8, 8, beta)
     if how == "evr":
         dm.EIGH = lambda L: sl.eigh(L, driver="evr")
+    elif how.startswith("gemmnoise_"):
+        # every pairwise contraction result scaled by (1 + 1e-15 z): the size of the rounding
+        # differences another FP64 summation order leaves in each contraction
+        rng = np.random.default_rng(int(how.rsplit("_", 1)[1]))
+        td = np.tensordot
+        dm.np.tensordot = lambda a, b, axes=2: (lambda r: r * (1.0 + 1e-15 * rng.standard_normal(r.shape)))(
+            td(a, b, axes=axes))
     else:
         amp = 1e-13 if how.startswith("perturbed13_") else 1e-15
         rng = np.random.default_rng(int(how.rsplit("_", 1)[1]))
@@ -102,9 +111,10 @@ def w3spread(out_path, betas, hows):
                   **{k: v for k, v in row.items() if k != "beta"}}
     json.dump({"workload": "8x8x8 lattice of w3_oracle.json, chi 16",
                "what": "largest |dlnZ|/N between the stored oracle value and the oracle under an "
-                       "alternative LAPACK eigensolver (evr), or relative input noise of 1e-15 "
+                       "alternative LAPACK eigensolver (evr), relative input noise of 1e-15 "
                        "(perturbed_s) or 1e-13 (perturbed13_s, the rounding bound of an FP64 sum "
-                       "of about 10^3 terms)",
+                       "of about 10^3 terms), or 1e-15 relative noise on every pairwise "
+                       "contraction result (gemmnoise_s, another summation order's rounding)",
                "rows": [old[b] for b in sorted(old)]}, open(out_path, "w"), indent=1)
 
 

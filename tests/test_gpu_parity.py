@@ -172,14 +172,19 @@ def test_w3_full_size_against_golden(T):
     values written by tests/golden/make_golden.py from the oracle (about 22 minutes each on
     8 host threads). Environments reach 2^27 elements: those ops run over the whole chip."""
     gold = json.load(open(os.path.join(HERE, "golden", "w3_oracle.json")))["rows"]
+    # where the oracle itself moves under another valid FP64 evaluation (w3_spread.json,
+    # make_golden.py w3spread), the bound is max(1e-10, 10 x that spread), as for the graphs
+    sp_path = os.path.join(HERE, "golden", "w3_spread.json")
+    spread = {r["beta"]: r["spread"] for r in json.load(open(sp_path))["rows"]} if os.path.exists(sp_path) else {}
     for g in gold:
         net = inputs.ising_3d(8, 8, 8, g["beta"])
         h = T.create_network(net)
         r = T.tn_contract_approx(h, net.slices, g["chi"], g["env"])
         d = abs(r.log_abs - g["log_abs"]) / net.n_sites
-        print(f"W3 beta={g['beta']} chi={g['chi']}: gpu {r.log_abs!r} oracle {g['log_abs']!r} diff/N {d:.3e}, "
-              f"{r.seconds:.2f} s", flush=True)
-        assert r.sign == g["sign"] and d <= TOL
+        bound = max(TOL, 10 * spread.get(g["beta"], 0.0))
+        print(f"W3 beta={g['beta']} chi={g['chi']}: gpu {r.log_abs!r} oracle {g['log_abs']!r} diff/N {d:.3e} "
+              f"(bound {bound:.1e}), {r.seconds:.2f} s", flush=True)
+        assert r.sign == g["sign"] and d <= bound
         del h
 
 
