@@ -704,15 +704,51 @@ __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double
 
 // ---------------------------------------------------------------- reductions
 
+// Cross-lane moves within a row of 16 lanes run on DPP (a VALU operand modifier) rather
+// than through the LDS crossbar that a general shuffle takes; both halves of a double
+// move with the same control. Every lane of a group ends with the same bits: each step
+// adds a lane's value and its partner's, in the same order on both sides.
+// Rows outside ROWS (a 4-bit mask of the wave's four rows of 16) receive 0.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppQuadXor1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowBcast15 = 0x142;   // lane 15 of each row to the next row
+constexpr int kDppRowBcast31 = 0x143;   // lane 31 to rows 2 and 3
+__device__ __forceinline__ double lane63(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+// sum over each aligned group of 4 lanes (all four active), in every lane of the group
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_f64<kDppQuadXor1>(v);
+  return v + dpp_f64<kDppQuadXor2>(v);
+}
+// whole-wave reductions (all lanes active): row results, then rows 1 and 3 take the rows
+// before them and row 3 the first two; lane 63's value is read back as a uniform scalar
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_f64<kDppQuadXor1>(v));
+  v = fmax(v, dpp_f64<kDppQuadXor2>(v));
+  v = fmax(v, dpp_f64<kDppRowHalfMirror>(v));
+  v = fmax(v, dpp_f64<kDppRowMirror>(v));
+  v = fmax(v, dpp_f64<kDppRowBcast15, 0xA>(v));
+  v = fmax(v, dpp_f64<kDppRowBcast31, 0xC>(v));
+  return lane63(v);
 }
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = quad_sum(v);
+  v += dpp_f64<kDppRowHalfMirror>(v);   // lane i of 8 takes lane 7 - i: the other quad
+  v += dpp_f64<kDppRowMirror>(v);       // lane i of 16 takes lane 15 - i: the other half row
+  v += dpp_f64<kDppRowBcast15, 0xA>(v); // rows 1, 3: rows 0 + 1, rows 2 + 3
+  v += dpp_f64<kDppRowBcast31, 0xC>(v); // row 3: all four rows
+  return lane63(v);
 }
 
 // block-wide reduction through 4 LDS slots; every thread gets the result
@@ -849,7 +885,7 @@ __device__ __noinline__ ChaseOut ql_chase(Pair *de_, Pair *rb_, Pair *spare_, in
   double pdx = 0.0, pdy = 0.0, prx = 0.0, pry = 0.0;
   int cnt = 0;
   bool live = true;
-  for (int i = mu - 1; i >= lu; --i) {
+  auto step = [&](int i) {
     const double ei = ne, di = nd;
     const int nxt = i > lu ? i - 1 : lu;
     nd = de[nxt].x;
@@ -890,7 +926,15 @@ __device__ __noinline__ ChaseOut ql_chase(Pair *de_, Pair *rb_, Pair *spare_, in
     cnt += live && !z ? 1 : 0;
     live = live && !z;
     di1 = di;
+  };
+  // two steps per trip: the prefetched pair and the pending writes change registers
+  // between the copies instead of being moved at the end of every step
+  int i = mu - 1;
+  for (; i - 1 >= lu; i -= 2) {
+    step(i);
+    step(i - 1);
   }
+  if (i >= lu) step(i);
   if (lane0) {
     pd->x = pdx;
     pd->y = pdy;
@@ -957,9 +1001,7 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
         a3 += row[k + 12] * vv[k + 12];
       }
       for (; k < m; k += 4) a0 += row[k] * vv[k];
-      double acc = (a0 + a1) + (a2 + a3);
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
+      const double acc = quad_sum((a0 + a1) + (a2 + a3));
       if (sub == 0) {
         pp[r] = beta * acc;
         vp += vv[r] * (beta * acc);
@@ -1175,10 +1217,7 @@ __device__ void back_transform(const EigWs &E, int k) {
         for (int c = 0; c < kWY; ++c) a[c] += Vb[c * n + i] * zi;
       }
 #pragma unroll
-      for (int c = 0; c < kWY; ++c) {
-        a[c] += __shfl_xor(a[c], 1, 64);
-        a[c] += __shfl_xor(a[c], 2, 64);
-      }
+      for (int c = 0; c < kWY; ++c) a[c] = quad_sum(a[c]);
       if (sub == 0) {
         if (task < k) {
 #pragma unroll
