@@ -827,7 +827,8 @@ struct EigWs {          // LDS work area of one solve of order n
   double *red;
   double *wq;           // 8n: QL's copy of (d, e) and rotation buffers; then reflector blocks
   double *gw;           // 24: Gram matrix and betas of a reflector block
-  double *hv;           // reflectors in global memory: v_j at hv[j*n + i], beta_j at hv[n*n + j]
+  double *hv;           // reflectors: v_j at hv[j*n + i], beta_j at hv[n*n + j] (LDS past the
+                        // work area when they fit, else the op's global scratch)
   int n, pa;
 };
 
@@ -1591,7 +1592,10 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
   const int ucols = op.K;
   const int tid = threadIdx.x;
   if (kp.model && eig_learned(op, ws, dyn, kp, sc, lds, n, ld, ucols)) return;
-  EigWs E = eig_ws(lds, n, ws + op.b);
+  // the reflectors stay in LDS when they fit beside the work area (n up to about 90): the
+  // reduction's writes and the back-transformation's reads then never wait on memory
+  const bool hv_lds = eig_lds_doubles(n) + n * n + n <= kLdsDoubles;
+  EigWs E = eig_ws(lds, n, hv_lds ? lds + eig_lds_doubles(n) : ws + op.b);
   const double *L = ws + op.a;
   long long t0 = wall_clock64();
   for (int e = tid; e < n * n; e += kThreads) {
