@@ -1104,10 +1104,25 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
         const int lu = __builtin_amdgcn_readfirstlane(l), mu = __builtin_amdgcn_readfirstlane(m);
         Pair *rb = rot + n * b;
         const double dl = de[lu].x, el = de[lu].y;
-        double g = (de[lu + 1].x - dl) / (2.0 * el);
-        double r = sqrt(g * g + 1.0);
-        double di1 = de[mu].x;
-        g = di1 - dl + el / (g + copysign(r, g));
+        const double di1 = de[mu].x;
+        // Wilkinson shift d_l - e_l / (g + sign(g) sqrt(g^2 + 1)), g = (d_{l+1} - d_l) / (2 e_l),
+        // written as d_l - 2 e_l^2 / (h + sign(h) sqrt(h^2 + 4 e_l^2)) with h = d_{l+1} - d_l: one
+        // square root and one reciprocal, both from hardware estimates with one Newton step
+        // (a shift only steers convergence, so 2^-46 relative suffices); the exact quotient
+        // form where the squares could underflow
+        const double h = de[lu + 1].x - dl, w = el + el;
+        const double s2 = fma(h, h, w * w);
+        double g;
+        if (s2 > 1e-280) {
+          const double y = __builtin_amdgcn_rsq(s2);
+          const double hyp = s2 * y * fma(-0.5 * s2 * y, y, 1.5);
+          const double den = h + copysign(hyp, h);
+          const double rd = __builtin_amdgcn_rcp(den);
+          g = di1 - dl + 2.0 * el * el * (rd * fma(-den, rd, 2.0));
+        } else {
+          const double g0 = h / w;
+          g = di1 - dl + el / (g0 + copysign(sqrt(g0 * g0 + 1.0), g0));
+        }
         const ChaseOut co = ql_chase(de, rb, spare, lu, mu, g, di1);
         const int cnt = co.cnt;
         nrot += cnt + co.split;
