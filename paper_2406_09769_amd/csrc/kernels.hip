@@ -1,12 +1,17 @@
 // kernels.hip - CDNA4 (gfx950) device code of the density-matrix contraction.
 //
 // One workgroup of 256 threads (4 wave64s) executes one network's op list:
-//   OP_GEMM     pairwise contraction as a 64x64-tiled FP64 GEMM on the matrix cores
-//               (v_mfma_f64_16x16x4f64); operand gathers through index tables fold
-//               every mode permutation into the tile loads.
+//   OP_GEMM     pairwise contraction as an FP64 GEMM on the matrix cores
+//               (v_mfma_f64_16x16x4f64), pipelined over (block, k-chunk) steps with one
+//               of six block shapes; operand gathers through index tables fold every
+//               mode permutation into the tile loads (split BF16x3 / FP16x3 forms on
+//               the 16-bit matrix cores).
 //   OP_EIG      symmetric eigensolve of a density matrix (Householder tridiagonal
-//               reduction, implicit QL, back-transformation of the kept vectors)
+//               reduction, implicit QL with one wave chasing and three applying the
+//               rotations, compact-WY back-transformation of the kept vectors)
 //               followed by the keep rule; writes the kept eigenvectors and rank.
+//               A learned warm start (subspace iteration from MLP-scored columns with
+//               a certificate) may replace the full solve.
 // MPS bonds have a runtime extent (the kept rank of the eigensolve that made them):
 // tensors keep their static layout and every op touches only the valid box.
 //   OP_RESCALE  exact power-of-two normalisation with the exponent summed in int64.
