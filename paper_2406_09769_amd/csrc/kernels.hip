@@ -780,6 +780,38 @@ __device__ void rescale_wg(const Op &op, double *x, NetScalars *sc, double *red)
   const int32_t R = box_eff(op.bm), Cn = box_eff(op.bnb);
   const int64_t ncols = op.count;
   const int64_t total = int64_t(R) * Cn;
+  // up to kCached elements per thread are held in registers between the two passes, so
+  // the scaling pass does not read the tensor again
+  constexpr int kCached = 16;
+  if (total <= int64_t(kCached) * kThreads) {
+    double v[kCached];
+    int64_t o[kCached];
+    double m = 0.0;
+#pragma unroll
+    for (int q = 0; q < kCached; ++q) {
+      const int32_t i = int32_t(threadIdx.x) + q * kThreads;
+      o[q] = 0;
+      v[q] = 0.0;
+      if (i < total) {
+        const int32_t r = i / Cn, c = i - r * Cn;
+        o[q] = int64_t(box_conv(op.bm, r)) * ncols + box_conv(op.bnb, c);
+        v[q] = x[o[q]];
+        m = fmax(m, fabs(v[q]));
+      }
+    }
+    m = block_max(m, red);
+    if (!(m > 0.0) || !isfinite(m)) {
+      if (m == 0.0 && accum && threadIdx.x == 0) sc->zero = 1;
+      return;
+    }
+    int e;
+    frexp(m, &e);
+#pragma unroll
+    for (int q = 0; q < kCached; ++q)
+      if (int32_t(threadIdx.x) + q * kThreads < total) x[o[q]] = ldexp(v[q], -e);
+    if (accum && threadIdx.x == 0) sc->exp_sum += e;
+    return;
+  }
   double m = 0.0;
   for (int64_t i = threadIdx.x; i < total; i += kThreads) {
     const int32_t r = int32_t(i / Cn), c = int32_t(i - int64_t(r) * Cn);
