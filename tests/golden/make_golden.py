@@ -68,7 +68,8 @@ def _w3_spread_one(args):
     a = 1e-15 ("perturbed_<seed>") or a = 1e-13 ("perturbed13_<seed>", the relative rounding
     bound of an FP64 sum of about 10^3 terms, the depth of this lattice's contractions), or
     the default solver with every pairwise contraction result scaled by (1 + 1e-15 z)
-    ("gemmnoise_<seed>")."""
+    ("gemmnoise_<seed>"), or the default solver on L + eps ||L|| S, S symmetric Gaussian of
+    unit spectral norm ("eignoise_<seed>")."""
     import copy
     import numpy as np
     import scipy.linalg as sl
@@ -76,6 +77,18 @@ def _w3_spread_one(args):
     net = inputs.ising_3d(8, 8, 8, beta)
     if how == "evr":
         dm.EIGH = lambda L: sl.eigh(L, driver="evr")
+    elif how.startswith("eignoise_"):
+        # every density matrix handed to the default solver with a symmetric perturbation of
+        # spectral norm eps * ||L||: the backward error any FP64 symmetric eigensolver is
+        # allowed (an absolute-accuracy solver may show all of it)
+        rng = np.random.default_rng(int(how.rsplit("_", 1)[1]))
+
+        def eigh_noisy(L):
+            Z = rng.standard_normal(L.shape)
+            S = 0.5 * (Z + Z.T)
+            S /= np.linalg.norm(S, 2)
+            return np.linalg.eigh(L + np.finfo(float).eps * np.linalg.norm(L, 2) * S)
+        dm.EIGH = eigh_noisy
     elif how.startswith("gemmnoise_"):
         # every pairwise contraction result scaled by (1 + 1e-15 z): the size of the rounding
         # differences another FP64 summation order leaves in each contraction
@@ -113,8 +126,10 @@ def w3spread(out_path, betas, hows):
                "what": "largest |dlnZ|/N between the stored oracle value and the oracle under an "
                        "alternative LAPACK eigensolver (evr), relative input noise of 1e-15 "
                        "(perturbed_s) or 1e-13 (perturbed13_s, the rounding bound of an FP64 sum "
-                       "of about 10^3 terms), or 1e-15 relative noise on every pairwise "
-                       "contraction result (gemmnoise_s, another summation order's rounding)",
+                       "of about 10^3 terms), 1e-15 relative noise on every pairwise "
+                       "contraction result (gemmnoise_s, another summation order's rounding), or "
+                       "a symmetric perturbation of norm eps ||L|| of every density matrix "
+                       "(eignoise_s, the backward error an FP64 eigensolver may have)",
                "rows": [old[b] for b in sorted(old)]}, open(out_path, "w"), indent=1)
 
 
