@@ -904,11 +904,11 @@ typedef __attribute__((address_space(3))) Pair lds_pair;
 // each rotation go to rb in order. The step carries no branch: an underflow (f = g = 0,
 // where T splits) writes the split values and turns the remaining steps into writes to
 // the spare pair `spare`, so the chase never waits on a scalar test of a vector result.
-// Kept out of line so that its few live values get registers of their own rather than
-// those of the large caller. Returns p and g of the last step, the rotations, and
+// The pointers are taken as LDS pointers, so every access is a ds_ instruction whatever
+// the caller's pointer provenance. Returns p and g of the last step, the rotations, and
 // whether T split.
 struct ChaseOut { double p, g; int cnt, split; };
-__device__ __noinline__ ChaseOut ql_chase(Pair *de_, Pair *rb_, Pair *spare_, int lu_, int mu_, double g,
+__device__ __forceinline__ ChaseOut ql_chase(Pair *de_, Pair *rb_, Pair *spare_, int lu_, int mu_, double g,
                                           double di1) {
   lds_pair *de = (lds_pair *)de_, *rb = (lds_pair *)rb_, *spare = (lds_pair *)spare_;   // all in LDS
   const bool lane0 = (threadIdx.x & 63) == 0;
