@@ -7,6 +7,8 @@ Calls only oracle/ (and the seeded input generators). Usage:
     python tests/golden/make_golden.py w4spread  # how far FP64 fixes each W4 result (see spread())
     python tests/golden/make_golden.py w5small   # 8 random 3-SAT formulas, n 50, m 150, chi 32
     python tests/golden/make_golden.py w5smallspread  # how far FP64 fixes each of those results
+    python tests/golden/make_golden.py w4eignoise      # add the eigensolver backward-error row to w4_spread
+    python tests/golden/make_golden.py w5smalleignoise # ... and to w5_small_spread
     python tests/golden/make_golden.py w3   # 8x8x8 3D Ising at the 3 betas, chi 16, plane slices
     python tests/golden/make_golden.py w3spread 0.25 [--hows=evr,perturbed_0,perturbed13_0]
                                             # how far FP64 fixes the W3 result at these betas
@@ -166,6 +168,50 @@ def _spread_one(i, kind="w4"):
     return row
 
 
+def _eignoise_one(args):
+    """Instance i of a batch workload under the default solver on L + eps ||L|| S for every
+    density matrix (S symmetric Gaussian of unit spectral norm, seed 0): the backward error
+    any FP64 symmetric eigensolver is allowed. Returns (i, |dlnZ|/N from the stored value)."""
+    import numpy as np
+    kind, i = args
+    if kind == "w4":
+        gold = json.load(open(os.path.join(HERE, "w4_oracle.json")))["rows"][i]
+        net, chi = inputs.rrg_batch(i + 1)[i], 64
+    else:
+        gold = json.load(open(os.path.join(HERE, "w5_small_oracle.json")))["rows"][i]
+        net, chi = inputs.csp_batch(i + 1, n_vars=50)[i], 32
+    assert net.name == gold["name"]
+    rng = np.random.default_rng(0)
+
+    def eigh_noisy(L):
+        Z = rng.standard_normal(L.shape)
+        S = 0.5 * (Z + Z.T)
+        S /= np.linalg.norm(S, 2)
+        return np.linalg.eigh(L + np.finfo(float).eps * np.linalg.norm(L, 2) * S)
+    dm.EIGH = eigh_noisy
+    try:
+        v = dm.contract_approx(net, chi, 1)[0]
+    finally:
+        dm.EIGH = np.linalg.eigh
+    d = abs(v - gold["log_abs"]) / net.n_sites
+    print(json.dumps({"kind": kind, "index": i, "eignoise_0": d}), flush=True)
+    return i, d
+
+
+def add_eignoise(kind, path, count, workers=4):
+    """Adds the eignoise_0 deviation to every row of a stored spread file and raises each
+    row's spread to it where it is larger."""
+    with Pool(workers) as pool:
+        res = dict(pool.map(_eignoise_one, [(kind, i) for i in range(count)]))
+    d = json.load(open(path))
+    for r in d["rows"]:
+        r["eignoise_0"] = res[r["index"]]
+        r["spread"] = max(r["spread"], r["eignoise_0"])
+    d["what"] += ("; eignoise_0: each density matrix given a symmetric perturbation of norm "
+                  "eps ||L|| before its eigensolve, the backward error any FP64 eigensolver may have")
+    json.dump(d, open(path, "w"), indent=1)
+
+
 def _spread_w5small(i):
     return _spread_one(i, "w5small")
 
@@ -240,3 +286,7 @@ if __name__ == "__main__":
         batch("w5small", 8, 32, os.path.join(HERE, "w5_small_oracle.json"))
     elif which == "w5smallspread":
         spread_w5small(os.path.join(HERE, "w5_small_spread.json"))
+    elif which == "w4eignoise":
+        add_eignoise("w4", os.path.join(HERE, "w4_spread.json"), 64)
+    elif which == "w5smalleignoise":
+        add_eignoise("w5small", os.path.join(HERE, "w5_small_spread.json"), 8)
