@@ -1,8 +1,8 @@
 """Reference for the learned warm start of the eigensolve (TEST INFRASTRUCTURE ONLY).
 
 The learned form replaces the full eigensolve of a density matrix L by a few steps
-of subspace iteration started from columns of L chosen by a small MLP (a north-star
-form; the paper always computes leading eigenvectors exactly). This module gives
+of subspace iteration started from columns of L chosen by a small MLP (an addition of
+this implementation; the paper always computes leading eigenvectors exactly). This module gives
 the plain numpy definition of every piece, independent of the GPU code:
 
 * row features of a density matrix (bond-local: diagonal weight, row weight,
