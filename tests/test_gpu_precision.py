@@ -54,9 +54,11 @@ def test_fp64_unchanged_by_the_option(T):
     assert a.log_abs == b.log_abs
 
 
+@pytest.mark.parametrize("tau_rel", [1e-15, 1e-10])
 @pytest.mark.parametrize("precision", [1, 2])
-def test_w2_full_size_precision_form(T, precision):
-    """All 32 networks of the 64x64 workload in one launch."""
+def test_w2_full_size_precision_form(T, precision, tau_rel):
+    """All 32 networks of the 64x64 workload in one launch, with the default keep cutoff and
+    with the 1e-10 cutoff the split forms use in the benchmark."""
     gold = json.load(open(os.path.join(HERE, "golden", "w2_oracle.json")))["rows"]
     nets, chis, envs, gl = [], [], [], []
     for chi, env in ((32, 1), (32, 2), (64, 1), (64, 2)):
@@ -66,24 +68,27 @@ def test_w2_full_size_precision_form(T, precision):
             envs.append(env)
             gl.append(next(x for x in gold if x["chi"] == chi and x["env"] == env and abs(x["beta"] - b) < 1e-12))
     hs = [T.create_network(n) for n in nets]
-    rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], chis, envs, precision=precision)
+    rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], chis, envs, precision=precision, tau_rel=tau_rel)
     errs = [abs(r.log_abs - g["log_abs"]) / 4096 for r, g in zip(rs, gl)]
-    print(f"64x64 workload, precision={precision}: kernel {rs[0].seconds:.3f} s, worst |dlnZ|/N {max(errs):.3e}, "
+    print(f"64x64 workload, precision={precision}, tau_rel={tau_rel:g}: kernel {rs[0].seconds:.3f} s, worst |dlnZ|/N {max(errs):.3e}, "
           f"per (chi, env) group {[f'{max(errs[8 * i:8 * i + 8]):.1e}' for i in range(4)]}", flush=True)
     assert all(r.sign == g["sign"] for r, g in zip(rs, gl))
     assert max(errs) <= BOUND
 
 
+@pytest.mark.parametrize("tau_rel", [1e-15, 1e-10])
 @pytest.mark.parametrize("precision", [1, 2])
-def test_w3_full_size_precision_form(T, precision):
-    """8x8x8 lattice, chi 16, the three betas, against the stored FP64 oracle values."""
+def test_w3_full_size_precision_form(T, precision, tau_rel):
+    """8x8x8 lattice, chi 16, the three betas, against the stored FP64 oracle values, with
+    the default keep cutoff and the split forms' 1e-10."""
     gold = json.load(open(os.path.join(HERE, "golden", "w3_oracle.json")))["rows"]
     for g in gold:
         net = inputs.ising_3d(8, 8, 8, g["beta"])
         h = T.create_network(net)
-        r = T.tn_contract_approx(h, net.slices, g["chi"], g["env"], precision=precision)
+        r = T.tn_contract_approx(h, net.slices, g["chi"], g["env"], precision=precision, tau_rel=tau_rel)
         d = abs(r.log_abs - g["log_abs"]) / net.n_sites
-        print(f"W3 beta={g['beta']} chi={g['chi']} precision={precision}: |dlnZ|/N {d:.3e}, {r.seconds:.2f} s",
+        print(f"W3 beta={g['beta']} chi={g['chi']} precision={precision} tau_rel={tau_rel:g}: |dlnZ|/N {d:.3e}, "
+              f"{r.seconds:.2f} s",
               flush=True)
         assert r.sign == g["sign"] and d <= BOUND
         del h
