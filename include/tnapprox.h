@@ -195,10 +195,12 @@ int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env
 /* C (M x N, row-major) = A B with A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn],
  * through the contraction GEMM in the given tn_precision (FP64 matrix cores, or the
  * split BF16 / FP16 products). lo_split sets the inner size of the two-level
- * row/column index maps. */
+ * row/column index maps. chip_wide = 0 runs the product in one workgroup, as a
+ * network's pass does; nonzero runs it over the whole chip with the launch a
+ * contraction too large for one workgroup gets. */
 int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, int64_t sbk,
                   int64_t sbn, double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split,
-                  int32_t precision);
+                  int32_t precision, int32_t chip_wide);
 
 /* U (n x ucols, row-major) = the kept leading eigenvectors of (L + L^T)/2 (n x n),
  * zero columns past the kept rank, under opt's tau_rel and tau_deg (NULL: defaults).

@@ -687,7 +687,7 @@ int tn_profile_last(tn_net net, double *seconds_by_kind) {
 // slots: the kept-rank slots (in: initial extents, default 1; out: as left by the ops).
 static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t> &tab, std::vector<double> &ws,
                       const std::vector<double> &cst, const tn::KeepParams &kp, tn::NetScalars *sc_out,
-                      std::vector<int32_t> *slots_io = nullptr) {
+                      std::vector<int32_t> *slots_io = nullptr, int grid_blocks = 0, bool grid_piped = false) {
   int rc = check_device();
   if (rc != TN_OK) return rc;
   tn::Op *d_ops = nullptr;
@@ -722,7 +722,9 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
   if (e == hipSuccess && !cst.empty()) e = hipMemcpy(d_cst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_sc, &init, sizeof(init), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_nd, &nd, sizeof(nd), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = tn::launch_interp(d_nd, 1, kp, nullptr);
+  if (e == hipSuccess)   // one op over the whole chip, else the interpreter's single workgroup
+    e = grid_blocks > 0 ? tn::launch_gemm_grid(d_nd, 0, grid_blocks, kp.split, grid_piped, nullptr)
+                        : tn::launch_interp(d_nd, 1, kp, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess && !ws.empty()) e = hipMemcpy(ws.data(), d_ws + 32, ws.size() * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess && sc_out) e = hipMemcpy(sc_out, d_sc, sizeof(tn::NetScalars), hipMemcpyDeviceToHost);
@@ -736,7 +738,8 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
 }
 
 int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, int64_t sbk, int64_t sbn,
-                  double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split, int32_t precision) {
+                  double *C, int32_t M, int32_t N, int32_t K, int32_t lo_split, int32_t precision,
+                  int32_t chip_wide) {
   g_err.clear();
   if (!A || !B || !C || M < 1 || N < 1 || K < 1) return fail(TN_EINVAL, "bad gemm arguments");
   if (precision < TN_FP64 || precision > TN_SPLIT_FP16X3) return fail(TN_EINVAL, "unknown precision");
@@ -775,7 +778,13 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
   std::vector<double> ws(int64_t(M) * N, 0.0);
   tn::KeepParams kp{1e-15, 1e-12, tn::kClusterFloor};
   kp.split = precision;
-  int rc = run_single({op}, tab, ws, cst, kp, nullptr);
+  int blocks = 0;
+  bool piped = false;
+  if (chip_wide) {   // the launch the planner gives a chip-wide contraction of this shape
+    blocks = int(std::min<int64_t>(tn::kGridBlocks, ((int64_t(M) + 63) / 64) * ((int64_t(N) + 63) / 64)));
+    piped = int64_t(M) + K <= int64_t(tn::kGridOffsetDoubles) && int64_t(M) * N < (int64_t(1) << 31);
+  }
+  int rc = run_single({op}, tab, ws, cst, kp, nullptr, nullptr, blocks, piped);
   if (rc != TN_OK) return rc;
   std::memcpy(C, ws.data(), ws.size() * 8);
   return TN_OK;

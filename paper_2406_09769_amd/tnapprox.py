@@ -71,7 +71,8 @@ def _load():
         "tn_last_error": (C.c_char_p, []),
         "tn_plan_stats": (C.c_int, [C.c_void_p, P(tn_path), C.c_int32, C.c_int32, P(C.c_int64)]),
         "tn_debug_gemm": (C.c_int, [P(C.c_double), C.c_int64, C.c_int64, P(C.c_double), C.c_int64, C.c_int64,
-                                    P(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+                                    P(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_int32]),
         "tn_debug_eig": (C.c_int, [P(C.c_double), C.c_int32, C.c_int32, C.c_int32, P(tn_options),
                                    P(C.c_double), P(C.c_int64)]),
         "tn_debug_rescale": (C.c_int, [P(C.c_double), C.c_int64, P(C.c_int64)]),
@@ -251,7 +252,8 @@ def tn_profile_last(h: Handle) -> dict:
             "learned_time": {"start": out[13], "products": out[14], "small_eig": out[15], "ritz": out[16]}}
 
 
-def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30, precision: int = TN_FP64) -> np.ndarray:
+def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30, precision: int = TN_FP64,
+                  chip_wide: bool = False) -> np.ndarray:
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     M, K = A.shape
@@ -261,7 +263,7 @@ def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30, precisi
     sbk, sbn = (s // 8 for s in B.strides)
     Cm = np.zeros((M, N))
     _check(LIB.tn_debug_gemm(_dptr(A), sam, sak, _dptr(B), sbk, sbn, _dptr(Cm), M, N, K, int(lo_split),
-                             int(precision)))
+                             int(precision), int(bool(chip_wide))))
     return Cm
 
 

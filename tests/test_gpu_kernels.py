@@ -118,3 +118,47 @@ def test_gemm_split_precision_within_its_bound(T, precision, M, N, K):
         # and it is not exact FP64 arithmetic in disguise: the error is at the split level
         if precision == 1 and scale == 1.0 and K >= 16:
             assert np.max(np.abs(C - ref)) > 0
+
+
+def _operands(M, N, K, layout, rng):
+    """A (M x K) and B (K x N) as views whose fast mode is k (A) / n (B) for "kn", or
+    m (A) / k (B) for "mk"."""
+    if layout == "kn":
+        return rng.standard_normal((M, K)), rng.standard_normal((K, N))
+    return rng.standard_normal((K, M)).T, rng.standard_normal((N, K)).T
+
+
+CHIP_SHAPES = [(1, 1, 1), (3, 257, 5), (64, 64, 16), (130, 200, 37), (300, 70, 1100), (700, 65, 600),
+               (70, 90, 2100)]
+
+
+@pytest.mark.parametrize("layout", ["kn", "mk"])
+@pytest.mark.parametrize("M,N,K", CHIP_SHAPES)
+def test_gemm_chip_wide_fp64(T, M, N, K, layout):
+    """The launch of a contraction too large for one workgroup (row + k offsets within
+    the LDS cache: pipelined tiles; else the plain tiled kernel), against numpy."""
+    rng = np.random.default_rng(M * 31 + N * 7 + K)
+    A, B = _operands(M, N, K, layout, rng)
+    C = T.tn_debug_gemm(A, B, chip_wide=True)
+    ref = A @ B
+    assert np.max(np.abs(C - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * max(1, K) ** 0.5
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("layout", ["kn", "mk"])
+@pytest.mark.parametrize("M,N,K", CHIP_SHAPES)
+def test_gemm_chip_wide_split_within_its_bound(T, precision, M, N, K, layout):
+    """Chip-wide split BF16 / FP16 products within |C - AB| <= 2^-20 (|A||B|), element by
+    element. Rows of A and columns of B are scaled by powers of two up to 2^±40 apart:
+    every row of an A chunk and every column of a B chunk carries its own scale, so the
+    bound holds however far apart their magnitudes lie (FP16 parts alone span 2^-24..2^16)."""
+    rng = np.random.default_rng(M * 13 + N * 5 + K + precision)
+    A, B = _operands(M, N, K, layout, rng)
+    A = A * np.exp(rng.uniform(-3, 0, A.shape)) * 2.0 ** rng.integers(-40, 41, (M, 1))
+    B = B * np.exp(rng.uniform(-3, 0, B.shape)) * 2.0 ** rng.integers(-40, 41, (1, N))
+    C = T.tn_debug_gemm(A, B, precision=precision, chip_wide=True)
+    ref = A @ B
+    bound = 2.0 ** -20 * (np.abs(A) @ np.abs(B))
+    assert np.all(np.abs(C - ref) <= bound + 1e-300), (precision, np.max(np.abs(C - ref) / bound))
+    if K >= 16:   # the split level, not FP64 arithmetic
+        assert np.max(np.abs(C - ref)) > 0
