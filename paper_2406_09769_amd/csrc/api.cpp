@@ -36,6 +36,8 @@ struct Seg {
   int64_t first, last;
   int blocks;
   bool piped;        // kind 1: offsets fit the pipelined chip-wide kernel
+  int64_t split_bytes = 0;   // kind 1: scratch of the split forms' operand planes
+  int split_blocks = 0;      // kind 1: workgroups of the split forms' operand pass
 };
 
 struct DevPlan {
@@ -96,12 +98,15 @@ struct tn_net_s {
   // scratch and a stream to capture the op launches on (all kept while the handle lives)
   tn::NetDev *d_nd = nullptr;
   double *d_part = nullptr;
+  unsigned short *d_split = nullptr;   // split forms: operand planes of the chip-wide GEMMs
+  int64_t split_cap = 0;
   hipStream_t cap_stream = nullptr;
   ~tn_net_s() {
     plans.clear();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (d_nd) (void)hipFree(d_nd);
     if (d_part) (void)hipFree(d_part);
+    if (d_split) (void)hipFree(d_split);
     if (d_const) (void)hipFree(d_const);
     if (d_ws) (void)hipFree(d_ws);
     if (d_sc) (void)hipFree(d_sc);
@@ -169,6 +174,10 @@ void make_segments(DevPlan &dp) {
     }
     if (kind) {
       segs.push_back(Seg{kind, i, i + 1, std::max(blocks, 1), piped});
+      if (kind == 1) {
+        segs.back().split_bytes = tn::split_scratch_bytes(op.am.n, op.bn.n, op.K);
+        segs.back().split_blocks = tn::split_grid_blocks(op.am.n, op.bn.n, op.K);
+      }
     } else if (!segs.empty() && segs.back().kind == 0) {
       segs.back().last = i + 1;
     } else {
@@ -232,7 +241,9 @@ tn_options defaults() {
 int launch_segments(tn_net net, DevPlan *dp, const tn::KeepParams &kp, hipStream_t st) {
   for (const Seg &sg : dp->segs) {
     if (sg.kind == 0) HIP_TRY(tn::launch_interp_range(net->d_nd, sg.first, sg.last, kp, st));
-    else if (sg.kind == 1) HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, sg.blocks, kp.split, sg.piped, st));
+    else if (sg.kind == 1)
+      HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, sg.blocks, kp.split, sg.piped, net->d_split, sg.split_blocks,
+                                   st));
     else HIP_TRY(tn::launch_rescale_grid(net->d_nd, sg.first, sg.blocks, net->d_part, st));
   }
   return TN_OK;
@@ -245,6 +256,20 @@ int run_stepwise(tn_net net, DevPlan *dp, const tn::NetDev &nd, const tn::KeepPa
     return fail(TN_ENOMEM, "descriptor allocation failed");
   if (!net->d_part && hipMalloc(&net->d_part, tn::kGridBlocks * sizeof(double)) != hipSuccess)
     return fail(TN_ENOMEM, "grid scratch allocation failed");
+  if (kp.split) {                           // planes for the largest chip-wide GEMM of the plan
+    int64_t need = 0;
+    for (const Seg &sg : dp->segs)
+      if (sg.kind == 1) need = std::max(need, sg.split_bytes);
+    if (need > net->split_cap) {
+      HIP_TRY(hipStreamSynchronize(st));    // earlier launches may still read the old planes
+      if (net->d_split) (void)hipFree(net->d_split);
+      net->d_split = nullptr;
+      net->split_cap = 0;
+      if (hipMalloc(&net->d_split, size_t(need)) != hipSuccess)
+        return fail(TN_ENOMEM, "split scratch allocation of " + std::to_string(need) + " bytes failed");
+      net->split_cap = need;
+    }
+  }
   HIP_TRY(hipMemcpyAsync(net->d_nd, &nd, sizeof(nd), hipMemcpyHostToDevice, st));
   std::vector<char> key;                    // the launch parameters, field by field (no padding)
   auto put = [&key](const void *p, size_t b) {
@@ -254,6 +279,7 @@ int run_stepwise(tn_net net, DevPlan *dp, const tn::NetDev &nd, const tn::KeepPa
   put(&kp.tau_rel, 8); put(&kp.tau_deg, 8); put(&kp.floor, 8); put(&kp.residual_tol, 8);
   put(&kp.model, sizeof(kp.model)); put(&kp.hx, sizeof(kp.hx)); put(&kp.hy, sizeof(kp.hy));
   put(&kp.hcount, sizeof(kp.hcount)); put(&kp.hcap, 8); put(&kp.split, 4); put(kp.gemm_cfg, 12);
+  put(&net->d_split, sizeof(net->d_split));
   if (!dp->gexec || dp->gkey != key) {
     if (dp->gexec) { (void)hipGraphExecDestroy(dp->gexec); dp->gexec = nullptr; }
     if (!net->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking));
@@ -695,9 +721,10 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
   double *d_ws = nullptr, *d_cst = nullptr;
   tn::NetScalars *d_sc = nullptr;
   tn::NetDev *d_nd = nullptr;
+  unsigned short *d_planes = nullptr;
   auto cleanup = [&]() {
     (void)hipFree(d_ops); (void)hipFree(d_tab); (void)hipFree(d_ws); (void)hipFree(d_cst);
-    (void)hipFree(d_sc); (void)hipFree(d_nd);
+    (void)hipFree(d_sc); (void)hipFree(d_nd); (void)hipFree(d_planes);
   };
   if (hipMalloc(&d_ops, ops.size() * sizeof(tn::Op)) != hipSuccess ||
       hipMalloc(&d_tab, std::max<size_t>(tab.size(), 1) * 4) != hipSuccess ||
@@ -722,8 +749,15 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
   if (e == hipSuccess && !cst.empty()) e = hipMemcpy(d_cst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_sc, &init, sizeof(init), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_nd, &nd, sizeof(nd), hipMemcpyHostToDevice);
+  int split_blocks = 0;
+  if (e == hipSuccess && grid_blocks > 0 && kp.split) {
+    const tn::Op &op = ops[0];
+    split_blocks = tn::split_grid_blocks(op.am.n, op.bn.n, op.K);
+    e = hipMalloc(&d_planes, size_t(tn::split_scratch_bytes(op.am.n, op.bn.n, op.K)));
+  }
   if (e == hipSuccess)   // one op over the whole chip, else the interpreter's single workgroup
-    e = grid_blocks > 0 ? tn::launch_gemm_grid(d_nd, 0, grid_blocks, kp.split, grid_piped, nullptr)
+    e = grid_blocks > 0 ? tn::launch_gemm_grid(d_nd, 0, grid_blocks, kp.split, grid_piped, d_planes, split_blocks,
+                                               nullptr)
                         : tn::launch_interp(d_nd, 1, kp, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess && !ws.empty()) e = hipMemcpy(ws.data(), d_ws + 32, ws.size() * 8, hipMemcpyDeviceToHost);

@@ -1638,198 +1638,176 @@ constexpr int kGridLds = 2 * kTK * kPitch + kKCache;   // gemm_tiles: two k-slic
 constexpr int kGridPipedTiles = piped_stage_doubles(32, 128, 16);   // largest chip-wide piped configuration
 constexpr int kGridLdsAll = kGridLds > kGridPipedTiles + kGridOffsetDoubles ? kGridLds : kGridPipedTiles + kGridOffsetDoubles;
 
-// Split-precision chip-wide GEMM: 64x64 output tiles in a grid stride, 16-deep k
-// chunks, one barrier per chunk. Each row of an A chunk (64 x 16) and each column of a
-// B chunk (16 x 64) gets its own power-of-two scale (its max |x| into [1/2, 1)), is split
-// into three parts in LDS, and the six part products of the chunk accumulate in FP32;
-// each output element adds the chunk's sum times the inverse scales of its row and
-// column to an FP64 accumulator. A row scale needs no barrier: its 16 values sit in one
-// 16-lane DPP row (k-fast operand) or in four lanes of one wave (free mode fastest).
-// Global loads run one chunk ahead of the MFMAs and the LDS stages alternate.
-constexpr int kSplitP = 20;                                      // 16 parts + 4 pad per row / column
-constexpr int kSplitPartDoubles = 6 * 64 * kSplitP / 4;          // 3 planes of A and of B, 16-bit words
-constexpr int kSplitStage = kSplitPartDoubles + 128;             // + inverse scales of 64 rows, 64 columns
-constexpr int kSplitKCache = 2048;                               // k offsets cached when K <= this
-constexpr int kSplitLds = 2 * kSplitStage + kSplitKCache;        // two stages + kA, kB as int32
+// Split-precision chip-wide GEMM in two passes.
+// split_operands_kernel: every (row of A, 16-deep k chunk) and every (column of B, chunk)
+// becomes one block of three planes of 16 parts (h, m, l as 16-bit words, 96 bytes) and
+// the inverse of its power-of-two scale (the block's max |x| into [1/2, 1)). Blocks are
+// chunk-major: A's (ch, row) at ch*M + row, then B's (ch, col) at M*nch + ch*N + col; the
+// FP64 inverse scales follow all blocks in the same order. Each value is split once.
+// gemm_presplit_kernel: 64x64 output tiles in a grid stride, 4 waves of 32x32; every lane
+// reads its MFMA operands straight from the planes (no LDS, no barrier), one chunk ahead,
+// sums the chunk's six part products in FP32 and adds that sum times its row's and
+// column's inverse scales to an FP64 accumulator.
+constexpr int kSplitBlockWords = 48;                             // 3 planes x 16 parts
+constexpr int kSplitKCache = 2048;                               // k offsets cached in LDS when K <= this
 
-__device__ __forceinline__ double row16_max(double v) {          // max over lanes 16r .. 16r + 15
-  v = fmax(v, dpp_f64<kDppQuadXor1>(v));
-  v = fmax(v, dpp_f64<kDppQuadXor2>(v));
-  v = fmax(v, dpp_f64<kDppRowHalfMirror>(v));
-  return fmax(v, dpp_f64<kDppRowMirror>(v));
-}
-
-template <int SPLIT, bool AKF, bool BNF>
-__device__ __forceinline__ void gemm_split_grid(const Op &op, const double *__restrict__ A,
-                                                const double *__restrict__ B, double *__restrict__ C,
-                                                const int32_t *__restrict__ tab, double *lds, NetScalars *sc) {
+template <int SPLIT>
+__global__ __launch_bounds__(kThreads) void split_operands_kernel(const NetDev *__restrict__ ndp, int64_t i,
+                                                                  unsigned short *__restrict__ planes) {
+  __shared__ int32_t kofs[2 * kSplitKCache];
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
+  const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
+  const int32_t *tab = nd.tab;
   const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
-  const int64_t NS = op.bn.n;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  if (blockIdx.x == 0 && tid == 0) sc->flops += 2LL * M * N * K;
-  int32_t *kA = reinterpret_cast<int32_t *>(lds + 2 * kSplitStage), *kB = kA + kSplitKCache;
+  const int nch = (K + 15) / 16;
   const bool kcached = K <= kSplitKCache;
   if (kcached) {
-    for (int k = tid; k < K; k += kThreads) {
+    for (int k = threadIdx.x; k < K; k += kThreads) {
       const int ks = box_conv(op.bk_, k);
-      kA[k] = tab[op.ak + ks];
-      kB[k] = tab[op.bk + ks];
+      kofs[k] = tab[op.ak + ks];
+      kofs[kSplitKCache + k] = tab[op.bk + ks];
     }
   }
   __syncthreads();
-  // (row, k) of this thread's 4 A elements and (column, k) of its 4 B elements in a chunk:
-  // 16 lanes along k for a k-fast operand, else 16 lanes along the row / column
-  constexpr bool akf = AKF, bnf = BNF;
-  int ri[4], rk[4], cj[4], ck[4];
+  const int64_t nA = int64_t(M) * nch, total = int64_t(M + N) * nch;
+  double *iscale = reinterpret_cast<double *>(planes + total * kSplitBlockWords);
+  for (int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x; t < total; t += int64_t(gridDim.x) * kThreads) {
+    const bool isA = t < nA;
+    const int64_t u = isA ? t : t - nA;
+    const int n = isA ? M : N;
+    const int ch = int(u / n), r = int(u - int64_t(ch) * n);
+    const double *X = isA ? A : B;
+    const int64_t off = isA ? map_off(tab, op.am, box_conv(op.bm, r)) : map_off(tab, op.bn, box_conv(op.bnb, r));
+    const int32_t *kc = kofs + (isA ? 0 : kSplitKCache);
+    const int32_t kt = isA ? op.ak : op.bk;
+    double x[16];
+    double mx = 0.0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    ri[q] = akf ? (tid >> 4) + 16 * q : 16 * wave + (lane & 15);
-    rk[q] = akf ? (tid & 15) : (lane >> 4) + 4 * q;
-    cj[q] = bnf ? 16 * wave + (lane & 15) : (tid >> 4) + 16 * q;
-    ck[q] = bnf ? (lane >> 4) + 4 * q : (tid & 15);
+    for (int j = 0; j < 16; ++j) {
+      const int k = 16 * ch + j;
+      x[j] = k < K ? X[off + (kcached ? kc[k] : tab[kt + box_conv(op.bk_, k)])] : 0.0;
+      mx = fmax(mx, fabs(x[j]));
+    }
+    int e;
+    frexp(mx, &e);                                  // 0 for an all-zero block
+    unsigned int w[24];                             // planes h, m, l: two parts per word
+#pragma unroll
+    for (int j = 0; j < 16; j += 2) {
+      unsigned short h0, m0, l0, h1, m1, l1;
+      split3<SPLIT>(ldexp(x[j], -e), h0, m0, l0);
+      split3<SPLIT>(ldexp(x[j + 1], -e), h1, m1, l1);
+      w[j / 2] = h0 | (unsigned(h1) << 16);
+      w[8 + j / 2] = m0 | (unsigned(m1) << 16);
+      w[16 + j / 2] = l0 | (unsigned(l1) << 16);
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(planes + t * kSplitBlockWords);
+#pragma unroll
+    for (int v = 0; v < 6; ++v) dst[v] = make_uint4(w[4 * v], w[4 * v + 1], w[4 * v + 2], w[4 * v + 3]);
+    iscale[t] = ldexp(1.0, e);
   }
-  const int tilesN = (N + 63) / 64, ntiles = ((M + 63) / 64) * tilesN;
+}
+
+template <int SPLIT>
+__global__ __launch_bounds__(kThreads, 2) void gemm_presplit_kernel(const NetDev *__restrict__ ndp, int64_t i,
+                                                                    const unsigned short *__restrict__ planes) {
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
+  const int64_t NS = op.bn.n;
+  double *C = nd.ws + op.c;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  if (blockIdx.x == 0 && tid == 0) nd.sc->flops += 2LL * M * N * K;
   const int nch = (K + 15) / 16;
-  const int mine = int(blockIdx.x) < ntiles ? (ntiles - 1 - int(blockIdx.x)) / int(gridDim.x) + 1 : 0;
-  const int steps = mine * nch;
-  int64_t aoff[4], boff[4];
-  bool av[4], bv[4];
-  auto offsets = [&](int j) {                       // row / column offsets of this block's j-th tile
-    const int tile = int(blockIdx.x) + j * int(gridDim.x);
-    const int m0 = (tile / tilesN) * 64, n0 = (tile % tilesN) * 64;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      av[q] = m0 + ri[q] < M;
-      aoff[q] = av[q] ? map_off(tab, op.am, box_conv(op.bm, m0 + ri[q])) : 0;
-      bv[q] = n0 + cj[q] < N;
-      boff[q] = bv[q] ? map_off(tab, op.bn, box_conv(op.bnb, n0 + cj[q])) : 0;
-    }
-  };
-  double va[4], vb[4];
-  auto load = [&](int ch) {
-    const int k0 = 16 * ch;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ka = k0 + rk[q], kb = k0 + ck[q];
-      va[q] = (av[q] && ka < K) ? A[aoff[q] + (kcached ? kA[ka] : tab[op.ak + box_conv(op.bk_, ka)])] : 0.0;
-      vb[q] = (bv[q] && kb < K) ? B[boff[q] + (kcached ? kB[kb] : tab[op.bk + box_conv(op.bk_, kb)])] : 0.0;
-    }
-  };
-  // frexp exponents of the row maxima of this thread's 4 values (k-fast: one row per
-  // value, over its DPP row; else one row, over the thread's values and lanes l ^ 16, l ^ 32)
-  auto exps = [&](const double *v, auto kfast, int *e) {
-    if (decltype(kfast)::value) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) frexp(row16_max(fabs(v[q])), &e[q]);
-    } else {
-      double m = fmax(fmax(fabs(v[0]), fabs(v[1])), fmax(fabs(v[2]), fabs(v[3])));
-      m = fmax(m, __shfl_xor(m, 16));
-      m = fmax(m, __shfl_xor(m, 32));
-      int e0;
-      frexp(m, &e0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) e[q] = e0;
-    }
-  };
-  double acc64[2][2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+  const int64_t nA = int64_t(M) * nch, total = int64_t(M + N) * nch;
+  const unsigned short *Ap = planes, *Bp = planes + nA * kSplitBlockWords;
+  const double *sA = reinterpret_cast<const double *>(planes + total * kSplitBlockWords), *sB = sA + nA;
+  const int kq = 4 * (lane >> 4);
+  const int tilesN = (N + 63) / 64, ntiles = ((M + 63) / 64) * tilesN;
   constexpr int NACC = SPLIT == 1 ? 1 : 3;
   constexpr int O1 = NACC > 1 ? 1 : 0, O2 = NACC > 1 ? 2 : 0;
-  constexpr int P = kSplitP;
-  if (steps > 0) {
-    offsets(0);
-    load(0);
-  }
-  for (int s = 0; s < steps; ++s) {
-    const int j = s / nch, ch = s - j * nch;
-    double *stage = lds + (s & 1) * kSplitStage;
-    unsigned short *a3 = reinterpret_cast<unsigned short *>(stage), *b3 = a3 + 3 * 64 * P;
-    double *ia = stage + kSplitPartDoubles, *ib = ia + 64;
-    {
-      int ea[4], eb[4];
-      exps(va, std::integral_constant<bool, AKF>(), ea);
-      exps(vb, std::integral_constant<bool, !BNF>(), eb);
+  struct Chunk {
+    unsigned long long a[2][3], b[2][3];            // [16-row / column block][plane]
+    double sa[2], sb[2];                            // inverse scales of this lane's row / column
+  };
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int m0 = (tile / tilesN) * 64 + wm * 32, n0 = (tile % tilesN) * 64 + wn * 32;
+    // this lane's operand rows of A and columns of B (also its output column)
+    const int ra0 = m0 + (lane & 15), ra1 = ra0 + 16, cb0 = n0 + (lane & 15), cb1 = cb0 + 16;
+    auto load = [&](int ch, Chunk &c) {
+      const int64_t ba = int64_t(ch) * M, bb = int64_t(ch) * N;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        unsigned short h, m, l;
-        split3<SPLIT>(ldexp(va[q], -ea[q]), h, m, l);
-        a3[ri[q] * P + rk[q]] = h;
-        a3[(64 + ri[q]) * P + rk[q]] = m;
-        a3[(128 + ri[q]) * P + rk[q]] = l;
-        if (rk[q] == 0) ia[ri[q]] = ldexp(1.0, ea[q]);
-        split3<SPLIT>(ldexp(vb[q], -eb[q]), h, m, l);
-        b3[cj[q] * P + ck[q]] = h;
-        b3[(64 + cj[q]) * P + ck[q]] = m;
-        b3[(128 + cj[q]) * P + ck[q]] = l;
-        if (ck[q] == 0) ib[cj[q]] = ldexp(1.0, eb[q]);
+      for (int a = 0; a < 2; ++a) {
+        const int r = a ? ra1 : ra0;
+        const unsigned short *p = Ap + (ba + r) * kSplitBlockWords + kq;
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl)
+          c.a[a][pl] = r < M ? *reinterpret_cast<const unsigned long long *>(p + 16 * pl) : 0ull;
+        c.sa[a] = r < M ? sA[ba + r] : 0.0;
       }
-    }
-    if (s + 1 < steps) {                            // the next chunk, maybe of the next tile
-      if (ch == nch - 1) offsets(j + 1);
-      load(ch == nch - 1 ? 0 : ch + 1);
-    }
-    __syncthreads();
-    const int kq = 4 * (lane >> 4);
-    unsigned long long ah[2], amid[2], al[2], bh[2], bmid[2], bl[2];
-    double rs[2][4], cs[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int r = wm * 32 + a * 16 + (lane & 15);
-      ah[a] = *reinterpret_cast<const unsigned long long *>(a3 + r * P + kq);
-      amid[a] = *reinterpret_cast<const unsigned long long *>(a3 + (64 + r) * P + kq);
-      al[a] = *reinterpret_cast<const unsigned long long *>(a3 + (128 + r) * P + kq);
+      for (int b = 0; b < 2; ++b) {
+        const int col = b ? cb1 : cb0;
+        const unsigned short *p = Bp + (bb + col) * kSplitBlockWords + kq;
 #pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) rs[a][r4] = ia[wm * 32 + a * 16 + kq + r4];
-    }
+        for (int pl = 0; pl < 3; ++pl)
+          c.b[b][pl] = col < N ? *reinterpret_cast<const unsigned long long *>(p + 16 * pl) : 0ull;
+        c.sb[b] = col < N ? sB[bb + col] : 0.0;
+      }
+    };
+    double acc64[2][2][4];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int c = wn * 32 + b * 16 + (lane & 15);
-      bh[b] = *reinterpret_cast<const unsigned long long *>(b3 + c * P + kq);
-      bmid[b] = *reinterpret_cast<const unsigned long long *>(b3 + (64 + c) * P + kq);
-      bl[b] = *reinterpret_cast<const unsigned long long *>(b3 + (128 + c) * P + kq);
-      cs[b] = ib[c];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+    Chunk cur, nxt;
+    if (nch > 0) load(0, cur);
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) load(ch + 1, nxt);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        double rs[4];                               // scales of output rows kq .. kq+3: lanes kq .. kq+3 hold them
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rs[r] = __shfl(cur.sa[a], kq + r);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          v4f acc[NACC];
+#pragma unroll
+          for (int o = 0; o < NACC; ++o) acc[o] = v4f{0.f, 0.f, 0.f, 0.f};
+          acc[O2] = mfma16<SPLIT>(cur.a[a][1], cur.b[b][1], acc[O2]);    // small terms first
+          acc[O2] = mfma16<SPLIT>(cur.a[a][2], cur.b[b][0], acc[O2]);
+          acc[O2] = mfma16<SPLIT>(cur.a[a][0], cur.b[b][2], acc[O2]);
+          acc[O1] = mfma16<SPLIT>(cur.a[a][1], cur.b[b][0], acc[O1]);
+          acc[O1] = mfma16<SPLIT>(cur.a[a][0], cur.b[b][1], acc[O1]);
+          acc[0] = mfma16<SPLIT>(cur.a[a][0], cur.b[b][0], acc[0]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double v = double(acc[0][r]);
+            if (NACC > 1) v += double(acc[O1][r]) * 0x1p-11 + double(acc[O2][r]) * 0x1p-22;
+            acc64[a][b][r] += v * (rs[r] * cur.sb[b]);
+          }
+        }
+      }
+      if (ch + 1 < nch) cur = nxt;
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        v4f acc[NACC];
-#pragma unroll
-        for (int o = 0; o < NACC; ++o) acc[o] = v4f{0.f, 0.f, 0.f, 0.f};
-        acc[O2] = mfma16<SPLIT>(amid[a], bmid[b], acc[O2]);    // small terms first
-        acc[O2] = mfma16<SPLIT>(al[a], bh[b], acc[O2]);
-        acc[O2] = mfma16<SPLIT>(ah[a], bl[b], acc[O2]);
-        acc[O1] = mfma16<SPLIT>(amid[a], bh[b], acc[O1]);
-        acc[O1] = mfma16<SPLIT>(ah[a], bmid[b], acc[O1]);
-        acc[0] = mfma16<SPLIT>(ah[a], bh[b], acc[0]);
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          double v = double(acc[0][r]);
-          if (NACC > 1) v += double(acc[O1][r]) * 0x1p-11 + double(acc[O2][r]) * 0x1p-22;
-          acc64[a][b][r] += v * (rs[a][r] * cs[b]);
+          const int row = m0 + a * 16 + kq + r;     // D: lane l, reg r = row 4(l/16) + r
+          const int col = n0 + b * 16 + (lane & 15);
+          if (row < M && col < N) C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = acc64[a][b][r];
         }
-      }
-    if (ch == nch - 1) {
-      const int tile = int(blockIdx.x) + j * int(gridDim.x);
-      const int m0 = (tile / tilesN) * 64, n0 = (tile % tilesN) * 64;
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = m0 + wm * 32 + a * 16 + kq + r;   // D: lane l, reg r = row 4(l/16) + r
-            const int col = n0 + wn * 32 + b * 16 + (lane & 15);
-            if (row < M && col < N) C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = acc64[a][b][r];
-            acc64[a][b][r] = 0.0;
-          }
-    }
   }
 }
 
@@ -1902,25 +1880,6 @@ __global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__res
   gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
 }
 
-// split-precision chip-wide GEMM: its own kernel, with the LDS of its two stages only,
-// so that three workgroups share a CU
-template <int SPLIT>
-__global__ __launch_bounds__(kThreads, 3) void gemm_grid_split_kernel(const NetDev *__restrict__ ndp, int64_t i) {
-  __shared__ double lds[kSplitLds];
-  __shared__ Op s_op;
-  const NetDev nd = *ndp;
-  stage_op(nd, i, s_op);
-  const Op &op = s_op;
-  const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
-  const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-  double *C = nd.ws + op.c;
-  const bool akf = (op.flags & F_A_KFAST) != 0, bnf = (op.flags & F_B_NFAST) != 0;
-  if (akf && bnf) gemm_split_grid<SPLIT, true, true>(op, A, B, C, nd.tab, lds, nd.sc);
-  else if (akf) gemm_split_grid<SPLIT, true, false>(op, A, B, C, nd.tab, lds, nd.sc);
-  else if (bnf) gemm_split_grid<SPLIT, false, true>(op, A, B, C, nd.tab, lds, nd.sc);
-  else gemm_split_grid<SPLIT, false, false>(op, A, B, C, nd.tab, lds, nd.sc);
-}
-
 // max |x| over this workgroup's share of the valid box -> partial[blockIdx.x]
 __global__ __launch_bounds__(kThreads) void rescale_max_kernel(const NetDev *__restrict__ ndp, int64_t i,
                                                                double *partial) {
@@ -1982,12 +1941,20 @@ hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, bool piped, hipStream_t stream) {
-  if (split == 1)
-    hipLaunchKernelGGL(gemm_grid_split_kernel<1>, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);
-  else if (split == 2)
-    hipLaunchKernelGGL(gemm_grid_split_kernel<2>, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);
-  else if (piped)
+hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, bool piped,
+                            unsigned short *planes, int split_blocks, hipStream_t stream) {
+  if (split == 1 || split == 2) {
+    if (!planes || split_blocks < 1) return hipErrorInvalidValue;
+    if (split == 1) {
+      hipLaunchKernelGGL(split_operands_kernel<1>, dim3(split_blocks), dim3(kThreads), 0, stream, nd_dev, i, planes);
+      hipLaunchKernelGGL(gemm_presplit_kernel<1>, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i,
+                         (const unsigned short *)planes);
+    } else {
+      hipLaunchKernelGGL(split_operands_kernel<2>, dim3(split_blocks), dim3(kThreads), 0, stream, nd_dev, i, planes);
+      hipLaunchKernelGGL(gemm_presplit_kernel<2>, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i,
+                         (const unsigned short *)planes);
+    }
+  } else if (piped)
     hipLaunchKernelGGL(gemm_grid_piped_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);
   else
     hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);

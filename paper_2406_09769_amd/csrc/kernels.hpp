@@ -56,7 +56,18 @@ hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last
 // piped: the op's static rows + k fit kGridOffsetDoubles doubles of int32 offset pairs
 // and its static output is below 2^31 elements (FP64 runs the pipelined kernel then).
 constexpr int kGridOffsetDoubles = 1216;
-hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, bool piped, hipStream_t stream);
+// split (1, 2): the operands are first split into planes (device scratch of at least
+// split_scratch_bytes of the op's static rows, columns and K; split_blocks workgroups),
+// then multiplied; hipErrorInvalidValue without them.
+inline int64_t split_scratch_bytes(int64_t rows, int64_t cols, int64_t K) {
+  return (rows + cols) * ((K + 15) / 16) * (96 + 8);   // three planes of 16 parts + an FP64 scale per block
+}
+inline int split_grid_blocks(int64_t rows, int64_t cols, int64_t K) {
+  const int64_t blocks = ((rows + cols) * ((K + 15) / 16) + 255) / 256;
+  return int(blocks < kGridBlocks ? (blocks < 1 ? 1 : blocks) : kGridBlocks);
+}
+hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, bool piped,
+                            unsigned short *planes, int split_blocks, hipStream_t stream);
 hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, double *partial, hipStream_t stream);
 
 }  // namespace tn
