@@ -108,7 +108,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM block autotuner (built-in shapes)")
     ap.add_argument("--cubic", type=int, default=0, metavar="CHI",
                     help="only contract the 8x8x8 3D lattice (beta 0.2217, plane slices) once at max_rank CHI "
-                         "in FP64 and print its time (the chip-wide op path) and exit")
+                         "and print its time (the chip-wide op path) and exit")
+    ap.add_argument("--cubic-precision", choices=["fp64", "bf16x3", "fp16x3"], default="fp64",
+                    help="contraction arithmetic of the --cubic run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a buffer of MIB MiB once on the GPU (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -117,13 +119,15 @@ def main():
         from paper_2406_09769_amd import inputs, tnapprox as T
         net = inputs.ising_3d(8, 8, 8, 0.2217)
         h = T.create_network(net)
+        prec = {"fp64": T.TN_FP64, "bf16x3": T.TN_SPLIT_BF16X3, "fp16x3": T.TN_SPLIT_FP16X3}[args.cubic_precision]
         stats = T.tn_plan_stats(h, net.slices, args.cubic, 1)
-        T.tn_contract_approx(h, net.slices, args.cubic, 1)          # plan, workspace, graph capture
+        T.tn_contract_approx(h, net.slices, args.cubic, 1, precision=prec)   # plan, workspace, graph capture
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = T.tn_contract_approx(h, net.slices, args.cubic, 1)
+        r = T.tn_contract_approx(h, net.slices, args.cubic, 1, precision=prec)
         dt = time.perf_counter() - t0
         print(json.dumps({"workload": "ising3d_8x8x8_open_J1_h0 beta 0.2217 plane slices", "chi": args.cubic,
+                          "precision": args.cubic_precision,
                           "seconds": round(dt, 4), "kernel_s": round(r.seconds, 4), "log_abs": r.log_abs,
                           "sign": r.sign, "gemm_flops": r.flops, "plan": stats}), flush=True)
         return
