@@ -1711,104 +1711,167 @@ __global__ __launch_bounds__(kThreads) void split_operands_kernel(const NetDev *
   }
 }
 
-template <int SPLIT>
-__global__ __launch_bounds__(kThreads, 2) void gemm_presplit_kernel(const NetDev *__restrict__ ndp, int64_t i,
-                                                                    const unsigned short *__restrict__ planes) {
-  __shared__ Op s_op;
-  const NetDev nd = *ndp;
-  stage_op(nd, i, s_op);
-  const Op &op = s_op;
-  const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
+// LDS doubles of one stage of presplit_tiles: the A and B blocks of a tile's chunk in
+// 16-byte pieces (96 bytes per block), then one FP64 inverse scale per block
+constexpr int presplit_stage_doubles(int MB, int NB) { return 13 * (MB + NB); }
+constexpr int kPresplitLds = 2 * presplit_stage_doubles(16, 256);   // the largest configuration below
+
+// MB x NB output tiles in a grid stride; 4 waves of TM x TN 16 x 16 MFMA tiles. Step s
+// = (j-th tile of this block, chunk): its pieces are fetched into registers during the
+// products of step s - 1 and written to the LDS stage of step s, one barrier per step.
+template <int SPLIT, int MB, int NB, int TM, int TN>
+__device__ __forceinline__ void presplit_tiles(const Op &op, const unsigned short *__restrict__ planes,
+                                               double *__restrict__ C, double *lds, int M, int N, int K) {
+  constexpr int WN = NB / (16 * TN);
+  static_assert((MB / (16 * TM)) * WN == 4, "4 waves per block");
+  constexpr int kPlanePieces = 6 * (MB + NB), kPieces = 7 * (MB + NB);
+  constexpr int kStage = presplit_stage_doubles(MB, NB);
+  constexpr int NQ = (kPieces + kThreads - 1) / kThreads;
   const int64_t NS = op.bn.n;
-  double *C = nd.ws + op.c;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  if (blockIdx.x == 0 && tid == 0) nd.sc->flops += 2LL * M * N * K;
+  const int wm = wave / WN, wn = wave % WN;
   const int nch = (K + 15) / 16;
   const int64_t nA = int64_t(M) * nch, total = int64_t(M + N) * nch;
   const unsigned short *Ap = planes, *Bp = planes + nA * kSplitBlockWords;
   const double *sA = reinterpret_cast<const double *>(planes + total * kSplitBlockWords), *sB = sA + nA;
   const int kq = 4 * (lane >> 4);
-  const int tilesN = (N + 63) / 64, ntiles = ((M + 63) / 64) * tilesN;
+  const int tilesN = (N + NB - 1) / NB, ntiles = ((M + MB - 1) / MB) * tilesN;
+  const int mine = int(blockIdx.x) < ntiles ? (ntiles - 1 - int(blockIdx.x)) / int(gridDim.x) + 1 : 0;
+  const int steps = mine * nch;
   constexpr int NACC = SPLIT == 1 ? 1 : 3;
   constexpr int O1 = NACC > 1 ? 1 : 0, O2 = NACC > 1 ? 2 : 0;
-  struct Chunk {
-    unsigned long long a[2][3], b[2][3];            // [16-row / column block][plane]
-    double sa[2], sb[2];                            // inverse scales of this lane's row / column
-  };
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int m0 = (tile / tilesN) * 64 + wm * 32, n0 = (tile % tilesN) * 64 + wn * 32;
-    // this lane's operand rows of A and columns of B (also its output column)
-    const int ra0 = m0 + (lane & 15), ra1 = ra0 + 16, cb0 = n0 + (lane & 15), cb1 = cb0 + 16;
-    auto load = [&](int ch, Chunk &c) {
-      const int64_t ba = int64_t(ch) * M, bb = int64_t(ch) * N;
+  // piece p = tid + 256 q: a 16-byte sixth of an A block (p < 6 MB) or of a B block, or
+  // an inverse scale (A's, then B's)
+  uint4 pv[NQ];
+  auto fetch = [&](int s) {
+    const int j = s / nch, ch = s - j * nch;
+    const int tile = int(blockIdx.x) + j * int(gridDim.x);
+    const int m0 = (tile / tilesN) * MB, n0 = (tile % tilesN) * NB;
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int r = a ? ra1 : ra0;
-        const unsigned short *p = Ap + (ba + r) * kSplitBlockWords + kq;
-#pragma unroll
-        for (int pl = 0; pl < 3; ++pl)
-          c.a[a][pl] = r < M ? *reinterpret_cast<const unsigned long long *>(p + 16 * pl) : 0ull;
-        c.sa[a] = r < M ? sA[ba + r] : 0.0;
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int col = b ? cb1 : cb0;
-        const unsigned short *p = Bp + (bb + col) * kSplitBlockWords + kq;
-#pragma unroll
-        for (int pl = 0; pl < 3; ++pl)
-          c.b[b][pl] = col < N ? *reinterpret_cast<const unsigned long long *>(p + 16 * pl) : 0ull;
-        c.sb[b] = col < N ? sB[bb + col] : 0.0;
-      }
-    };
-    double acc64[2][2][4];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
-    Chunk cur, nxt;
-    if (nch > 0) load(0, cur);
-    for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) load(ch + 1, nxt);
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        double rs[4];                               // scales of output rows kq .. kq+3: lanes kq .. kq+3 hold them
-#pragma unroll
-        for (int r = 0; r < 4; ++r) rs[r] = __shfl(cur.sa[a], kq + r);
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          v4f acc[NACC];
-#pragma unroll
-          for (int o = 0; o < NACC; ++o) acc[o] = v4f{0.f, 0.f, 0.f, 0.f};
-          acc[O2] = mfma16<SPLIT>(cur.a[a][1], cur.b[b][1], acc[O2]);    // small terms first
-          acc[O2] = mfma16<SPLIT>(cur.a[a][2], cur.b[b][0], acc[O2]);
-          acc[O2] = mfma16<SPLIT>(cur.a[a][0], cur.b[b][2], acc[O2]);
-          acc[O1] = mfma16<SPLIT>(cur.a[a][1], cur.b[b][0], acc[O1]);
-          acc[O1] = mfma16<SPLIT>(cur.a[a][0], cur.b[b][1], acc[O1]);
-          acc[0] = mfma16<SPLIT>(cur.a[a][0], cur.b[b][0], acc[0]);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            double v = double(acc[0][r]);
-            if (NACC > 1) v += double(acc[O1][r]) * 0x1p-11 + double(acc[O2][r]) * 0x1p-22;
-            acc64[a][b][r] += v * (rs[r] * cur.sb[b]);
-          }
+    for (int q = 0; q < NQ; ++q) {
+      const int p = tid + kThreads * q;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (p < 6 * MB) {
+        const int blk = p / 6;
+        if (m0 + blk < M)
+          v = *reinterpret_cast<const uint4 *>(Ap + (int64_t(ch) * M + m0 + blk) * kSplitBlockWords + (p - 6 * blk) * 8);
+      } else if (p < kPlanePieces) {
+        const int pb = p - 6 * MB, blk = pb / 6;
+        if (n0 + blk < N)
+          v = *reinterpret_cast<const uint4 *>(Bp + (int64_t(ch) * N + n0 + blk) * kSplitBlockWords + (pb - 6 * blk) * 8);
+      } else if (p < kPieces) {
+        const int r = p - kPlanePieces;
+        double d = 0.0;
+        if (r < MB) {
+          if (m0 + r < M) d = sA[int64_t(ch) * M + m0 + r];
+        } else if (n0 + r - MB < N) {
+          d = sB[int64_t(ch) * N + n0 + r - MB];
         }
+        const unsigned long long u = (unsigned long long)__double_as_longlong(d);
+        v.x = unsigned(u);
+        v.y = unsigned(u >> 32);
       }
-      if (ch + 1 < nch) cur = nxt;
+      pv[q] = v;
+    }
+  };
+  auto stash = [&](double *stage) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int p = tid + kThreads * q;
+      if (p < kPlanePieces) reinterpret_cast<uint4 *>(stage)[p] = pv[q];
+      else if (p < kPieces)
+        stage[2 * kPlanePieces + (p - kPlanePieces)] =
+            __longlong_as_double((long long)(((unsigned long long)pv[q].y << 32) | pv[q].x));
+    }
+  };
+  double acc64[TM][TN][4];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
+  if (steps > 0) fetch(0);
+  for (int s = 0; s < steps; ++s) {
+    const int j = s / nch, ch = s - j * nch;
+    double *stage = lds + (s & 1) * kStage;
+    stash(stage);
+    __syncthreads();
+    if (s + 1 < steps) fetch(s + 1);               // in flight during the products
+    const unsigned short *a3 = reinterpret_cast<const unsigned short *>(stage), *b3 = a3 + MB * kSplitBlockWords;
+    const double *ia = stage + 2 * kPlanePieces, *ib = ia + MB;
+    unsigned long long av[TM][3], bv[TN][3];
+    double rs[TM][4], cs[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int r = wm * 16 * TM + a * 16 + (lane & 15);
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl)
+        av[a][pl] = *reinterpret_cast<const unsigned long long *>(a3 + r * kSplitBlockWords + 16 * pl + kq);
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) rs[a][r4] = ia[wm * 16 * TM + a * 16 + kq + r4];
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < TN; ++b) {
+      const int c = wn * 16 * TN + b * 16 + (lane & 15);
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int pl = 0; pl < 3; ++pl)
+        bv[b][pl] = *reinterpret_cast<const unsigned long long *>(b3 + c * kSplitBlockWords + 16 * pl + kq);
+      cs[b] = ib[c];
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        v4f acc[NACC];
+#pragma unroll
+        for (int o = 0; o < NACC; ++o) acc[o] = v4f{0.f, 0.f, 0.f, 0.f};
+        acc[O2] = mfma16<SPLIT>(av[a][1], bv[b][1], acc[O2]);    // small terms first
+        acc[O2] = mfma16<SPLIT>(av[a][2], bv[b][0], acc[O2]);
+        acc[O2] = mfma16<SPLIT>(av[a][0], bv[b][2], acc[O2]);
+        acc[O1] = mfma16<SPLIT>(av[a][1], bv[b][0], acc[O1]);
+        acc[O1] = mfma16<SPLIT>(av[a][0], bv[b][1], acc[O1]);
+        acc[0] = mfma16<SPLIT>(av[a][0], bv[b][0], acc[0]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = m0 + a * 16 + kq + r;     // D: lane l, reg r = row 4(l/16) + r
-          const int col = n0 + b * 16 + (lane & 15);
-          if (row < M && col < N) C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = acc64[a][b][r];
+          double v = double(acc[0][r]);
+          if (NACC > 1) v += double(acc[O1][r]) * 0x1p-11 + double(acc[O2][r]) * 0x1p-22;
+          acc64[a][b][r] += v * (rs[a][r] * cs[b]);
         }
+      }
+    if (ch == nch - 1) {
+      const int tile = int(blockIdx.x) + j * int(gridDim.x);
+      const int m0 = (tile / tilesN) * MB + wm * 16 * TM, n0 = (tile % tilesN) * NB + wn * 16 * TN;
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = m0 + a * 16 + kq + r;   // D: lane l, reg r = row 4(l/16) + r
+            const int col = n0 + b * 16 + (lane & 15);
+            if (row < M && col < N) C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = acc64[a][b][r];
+            acc64[a][b][r] = 0.0;
+          }
+    }
   }
+}
+
+// the output tile follows the op's runtime row count, as in the FP64 pipelined path
+template <int SPLIT>
+__global__ __launch_bounds__(kThreads, 2) void gemm_presplit_kernel(const NetDev *__restrict__ ndp, int64_t i,
+                                                                    const unsigned short *__restrict__ planes) {
+  __shared__ __attribute__((aligned(16))) double lds[kPresplitLds];
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
+  if (blockIdx.x == 0 && threadIdx.x == 0) nd.sc->flops += 2LL * M * N * K;
+  double *C = nd.ws + op.c;
+  if (M <= 16) presplit_tiles<SPLIT, 16, 256, 1, 4>(op, planes, C, lds, M, N, K);
+  else if (M <= 32) presplit_tiles<SPLIT, 32, 128, 2, 2>(op, planes, C, lds, M, N, K);
+  else presplit_tiles<SPLIT, 64, 64, 2, 2>(op, planes, C, lds, M, N, K);
 }
 
 // FP64 chip-wide GEMM through the pipelined path: k and row offsets cached in LDS,

@@ -128,8 +128,8 @@ def _operands(M, N, K, layout, rng):
     return rng.standard_normal((K, M)).T, rng.standard_normal((N, K)).T
 
 
-CHIP_SHAPES = [(1, 1, 1), (3, 257, 5), (64, 64, 16), (130, 200, 37), (300, 70, 1100), (700, 65, 600),
-               (70, 90, 2100)]
+CHIP_SHAPES = [(1, 1, 1), (3, 257, 5), (16, 513, 17), (20, 300, 40), (32, 129, 33), (64, 64, 16), (130, 200, 37),
+               (300, 70, 1100), (700, 65, 600), (70, 90, 2100)]
 
 
 @pytest.mark.parametrize("layout", ["kn", "mk"])
