@@ -66,9 +66,14 @@ __device__ __forceinline__ int32_t box_conv(const Box &b, int32_t i) {
 
 constexpr int kKCache = 4096;          // k offsets cached in LDS when K <= kKCache
 
-__device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
-                           double *__restrict__ C, const int32_t *__restrict__ tab, double *lds,
-                           int t_begin, int t_step, NetScalars *sc) {
+// Plain tiled GEMM (64x64 output tiles from t_begin in steps of t_step, 16-deep k
+// slices): the fallback for ops whose offsets do not fit the pipelined path's caches.
+// The k offsets of both operands are cached in LDS when K <= KCACHE (lds holds two
+// k-slices, then 2 KCACHE int32). Kept out of line, as one body per cache size.
+template <int KCACHE>
+__device__ __noinline__ void gemm_tiles_k(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
+                                          double *__restrict__ C, const int32_t *__restrict__ tab, double *lds,
+                                          int t_begin, int t_step, NetScalars *sc) {
   // runtime extents; the output keeps its static row length
   const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
   const int NS = op.bn.n;
@@ -78,12 +83,12 @@ __device__ void gemm_tiles(const Op &op, const double *__restrict__ A, const dou
   double *As = lds;                  // [kTK][kPitch], element (k, m)
   double *Bs = lds + kTK * kPitch;   // [kTK][kPitch], element (k, n)
   int32_t *kA = reinterpret_cast<int32_t *>(lds + 2 * kTK * kPitch);   // A's k offsets
-  int32_t *kB = kA + kKCache;                                          // B's k offsets
+  int32_t *kB = kA + KCACHE;                                           // B's k offsets
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const bool akf = (op.flags & F_A_KFAST) != 0;
   const bool bnf = (op.flags & F_B_NFAST) != 0;
-  const bool kcached = K <= kKCache;
+  const bool kcached = K <= KCACHE;
   if (kcached) {
     for (int k = tid; k < K; k += kThreads) {
       const int ks = box_conv(op.bk_, k);
@@ -511,7 +516,7 @@ static_assert(2 * split_stage_words(32, 128, 16) <= 4 * (kPipedTiles - 8), "spli
 static_assert(2 * split_stage_words(16, 256, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
 
 // One GEMM op. Returns false when its offsets do not fit the LDS cache (the caller
-// then runs gemm_tiles).
+// then runs gemm_tiles_k).
 __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
                         double *__restrict__ C, const int32_t *__restrict__ tab, double *lds, NetScalars *sc,
                         int split, const int *cfgs) {
@@ -1603,7 +1608,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
         const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
         const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
         if (!gemm_op(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc, kp.split, kp.gemm_cfg))
-          gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1, nd.sc);
+          gemm_tiles_k<kKCache>(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1, nd.sc);
         break;
       }
       case OP_EIG:
@@ -1634,7 +1639,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
 // over the whole chip: every workgroup stages the op, then takes output tiles or
 // elements in a stride of the grid.
 
-constexpr int kGridLds = 2 * kTK * kPitch + kKCache;   // gemm_tiles: two k-slices and both k caches
+constexpr int kGridLds = 2 * kTK * kPitch + kKCache;   // gemm_tiles_k<kKCache>: two k-slices and both k caches
 constexpr int kGridPipedTiles = piped_stage_doubles(32, 128, 16);   // largest chip-wide piped configuration
 constexpr int kGridLdsAll = kGridLds > kGridPipedTiles + kGridOffsetDoubles ? kGridLds : kGridPipedTiles + kGridOffsetDoubles;
 
@@ -1931,8 +1936,12 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_grid_piped_kernel(const NetD
   gemm_grid_piped(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc);
 }
 
+// FP64 chip-wide GEMM whose offsets do not fit the pipelined path: the tiled GEMM with
+// k offsets cached up to K = kGridKCache (the 3D environments contract over K = 8192)
+constexpr int kGridKCache = 8192;
+constexpr int kGridTilesLds = 2 * kTK * kPitch + kGridKCache;
 __global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__restrict__ ndp, int64_t i) {
-  __shared__ double lds[kGridLdsAll];
+  __shared__ double lds[kGridTilesLds > kGridLdsAll ? kGridTilesLds : kGridLdsAll];
   __shared__ Op s_op;
   const NetDev nd = *ndp;
   stage_op(nd, i, s_op);
@@ -1940,7 +1949,7 @@ __global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__res
   const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
   const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
   if (gemm_grid_piped(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc)) return;
-  gemm_tiles(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
+  gemm_tiles_k<kGridKCache>(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
 }
 
 // max |x| over this workgroup's share of the valid box -> partial[blockIdx.x]
