@@ -33,7 +33,7 @@ CUS = 256
 # HBM bytes per launch of interp_kernel on this workload: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (factors from a 256 MiB copy), from profiles/interp_kernel_w2_64x64_fp64_hbm.txt. Set to
 # None whenever the kernel changes until the counters are taken again.
-TRAFFIC_BYTES = 6.950e9
+TRAFFIC_BYTES = 6.953e9
 SPLIT_TAU_REL = 1e-10   # keep cutoff of the split-precision forms (relative to the largest eigenvalue)
 
 
