@@ -129,7 +129,7 @@ def _operands(M, N, K, layout, rng):
 
 
 CHIP_SHAPES = [(1, 1, 1), (3, 257, 5), (16, 513, 17), (20, 300, 40), (32, 129, 33), (64, 64, 16), (130, 200, 37),
-               (300, 70, 1100), (700, 65, 600), (70, 90, 2100)]
+               (300, 70, 1100), (700, 65, 600), (70, 90, 2100), (40, 33, 10300)]
 
 
 @pytest.mark.parametrize("layout", ["kn", "mk"])
