@@ -187,8 +187,9 @@ const char *tn_last_error(void);
 /* Plan statistics for (path, max_rank, env_size) on net: stats[0..7] = op count,
  * index-table entries, workspace doubles, GEMM flops (sum 2mnk), eigensolver flops
  * (9 n^3 per density matrix), density matrices, largest density-matrix dimension,
- * ops run over the whole chip (contractions or rescalings whose output exceeds 2^21
- * elements; a network with none runs in one workgroup's pass). */
+ * ops run over the whole chip (in a network with an op whose output exceeds 2^21
+ * elements: every contraction or rescaling with at least 2^13 output elements and every
+ * contraction of at least 2^24 flops; a network with none runs in one workgroup's pass). */
 int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size,
                   int64_t *stats);
 

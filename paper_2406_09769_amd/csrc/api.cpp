@@ -139,13 +139,13 @@ int64_t box_static(const tn::Box &b) {
 }
 
 // A network with an op whose output exceeds 2^21 elements (or a GEMM above 2^32 flops)
-// runs op by op. In such a network every op with an output of at least 2^15 elements
-// (or a GEMM of at least 2^26 flops) runs over the whole chip, the rest in single-
+// runs op by op. In such a network every op with an output of at least 2^13 elements
+// (or a GEMM of at least 2^24 flops) runs over the whole chip, the rest in single-
 // workgroup stretches between them. Networks without such ops keep the one-pass
 // interpreter.
 void make_segments(DevPlan &dp) {
   constexpr int64_t kBigOut = int64_t(1) << 21, kBigFlops = int64_t(1) << 32;
-  constexpr int64_t kGridOut = int64_t(1) << 15, kGridFlops = int64_t(1) << 26;
+  constexpr int64_t kGridOut = int64_t(1) << 13, kGridFlops = int64_t(1) << 24;
   const auto &ops = dp.plan.ops;
   auto out_of = [](const tn::Op &op) -> int64_t {
     if (op.kind == tn::OP_GEMM) return int64_t(op.am.n) * op.bn.n;
