@@ -246,9 +246,39 @@ class Builder {
     return int32_t(p_.ops.size() - 1);
   }
 
+  // Element count of a shape, saturated at k32 (no int64 overflow for long shapes).
+  static constexpr int64_t k32 = int64_t(1) << 31;
+  static int64_t sat_size(const std::vector<int64_t> &dim) {
+    int64_t s = 1;
+    for (int64_t d : dim) {
+      if (s >= k32 / d + 1) return k32;
+      s *= d;
+    }
+    return s;
+  }
+
   // Pairwise contraction over all shared labels; A's free modes come first. Within
   // each index group (A-free, shared, B-free) bond modes are placed first.
+  // Index maps, table entries and an op's row, column and contraction extents are
+  // int32 on the device, so a contraction whose operands, result or contraction
+  // extent reach 2^31 elements is refused (the plan fails as unsupported).
   Sym contract_ab(const Sym &A, const Sym &B) {
+    {
+      std::vector<int64_t> od, kd;
+      for (size_t i = 0; i < A.lab.size(); ++i) (B.find(A.lab[i]) >= 0 ? kd : od).push_back(A.dim[i]);
+      for (size_t i = 0; i < B.lab.size(); ++i)
+        if (A.find(B.lab[i]) < 0) od.push_back(B.dim[i]);
+      if (sat_size(A.dim) >= k32 || sat_size(B.dim) >= k32 || sat_size(od) >= k32 || sat_size(kd) >= k32) {
+        if (err.empty()) err = "a contraction operand or result reaches 2^31 elements";
+        Sym out;                 // a placeholder with the result's labels; no op is emitted
+        for (size_t i = 0; i < A.lab.size(); ++i)
+          if (B.find(A.lab[i]) < 0) { out.lab.push_back(A.lab[i]); out.dim.push_back(1); }
+        for (size_t i = 0; i < B.lab.size(); ++i)
+          if (A.find(B.lab[i]) < 0) { out.lab.push_back(B.lab[i]); out.dim.push_back(1); }
+        out.buf = new_buf(1);
+        return out;
+      }
+    }
     Group ga, gk, gb;
     auto sa = strides_of(A), sb = strides_of(B);
     for (size_t i = 0; i < A.lab.size(); ++i) {
@@ -357,6 +387,7 @@ class Builder {
   }
 
   Sym ident(int64_t d, int64_t l0, int64_t l1) {
+    if (d >= 46341 && err.empty()) err = "an identity of more than 2^31 elements";
     Sym s;
     s.lab = {l0, l1};
     s.dim = {d, d};

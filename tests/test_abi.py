@@ -113,3 +113,21 @@ def test_create_validates_before_touching_a_device(T):
 def test_error_strings(T):
     for s in range(6):
         assert T.LIB.tn_error_string(s)
+
+
+def _twin_block(order):
+    """Two order-`order` tensors joined by `order` bond-2 edges, absorbed one at a time: the
+    right environment of the first cut spans 2^(2 (order - 2)) elements even at rank 1."""
+    shapes = [(2,) * order, (2,) * order]
+    edges = [(0, m, 1, m) for m in range(order)]
+    return shapes, edges, [[0], [1]]
+
+
+def test_plan_refuses_intermediates_of_2_to_the_31_elements(T):
+    shapes, edges, slices = _twin_block(17)            # largest environment 2^30: planned
+    T.tn_plan_json(shapes, edges, slices, 1)
+    shapes, edges, slices = _twin_block(18)            # 2^32: refused before any table is built
+    with pytest.raises(T.TnError) as e:
+        T.tn_plan_json(shapes, edges, slices, 1)
+    assert e.value.status == T.TN_EUNSUPPORTED
+    assert "2^31" in str(e.value)
