@@ -62,11 +62,17 @@ typedef struct {
 
 typedef enum {
   TN_FP64 = 0,          /* every contraction in FP64 on the FP64 matrix cores */
-  TN_SPLIT_BF16X3 = 1,  /* contractions on the BF16 matrix cores: each operand scaled by a
-                           power of two to max |x| in [1/2, 1), split into three BF16 parts,
-                           the six part products of order <= 2 accumulated in FP32; the
-                           eigensolve, rescaling and log accumulation stay FP64 */
-  TN_SPLIT_FP16X3 = 2   /* the same with FP16 parts on the FP16 matrix cores */
+  TN_SPLIT_BF16X3 = 1,  /* the contractions that build right environments and density
+                           matrices (Eq. dm_cache and the density matrix definition) run on
+                           the BF16 matrix cores: each operand scaled by a power of two to
+                           max |x| in [1/2, 1), split into three BF16 parts, the six part
+                           products of order <= 2 accumulated in FP32. Their rounding only
+                           moves the kept subspaces. The main chain (projector application,
+                           the carried block, closing contractions), the eigensolve,
+                           rescaling and log accumulation stay FP64. */
+  TN_SPLIT_FP16X3 = 2,  /* the same with FP16 parts on the FP16 matrix cores */
+  TN_SPLIT_BF16X3_ALL = 3, /* BF16 x3 split on every contraction, the main chain included */
+  TN_SPLIT_FP16X3_ALL = 4  /* FP16 x3 split on every contraction */
 } tn_precision;
 
 typedef enum {

@@ -187,29 +187,40 @@ void make_segments(DevPlan &dp) {
   dp.segs = std::move(segs);
 }
 
+// The plan of (slices, chi, env) on the handle, built on first use. `device`: also give
+// it device copies of its op list and index tables (the allocation-free entry point
+// passes false and copies them into its scratch instead).
 int get_plan(tn_net net, const std::vector<std::vector<int32_t>> &slices, int32_t chi, int32_t env,
-             DevPlan **out) {
+             DevPlan **out, bool device = true) {
   PlanKey key{slices, chi, env};
   auto it = net->plans.find(key);
-  if (it != net->plans.end()) { *out = it->second.get(); return TN_OK; }
-  auto dp = std::make_unique<DevPlan>();
-  tn::PlanArgs pa;
-  pa.slices = slices;
-  pa.chi = chi;
-  pa.env = env;
-  bool unsup = false;
-  std::string err = tn::make_plan(net->g, pa, dp->plan, &unsup);
-  if (!err.empty()) return fail(unsup ? TN_EUNSUPPORTED : TN_EINVAL, err);
-  make_segments(*dp);
-  size_t ob = dp->plan.ops.size() * sizeof(tn::Op), tb = std::max<size_t>(1, dp->plan.tables.size()) * 4;
-  if (hipMalloc(&dp->d_ops, std::max<size_t>(ob, 64)) != hipSuccess ||
-      hipMalloc(&dp->d_tab, tb) != hipSuccess)
-    return fail(TN_ENOMEM, "device allocation for the plan failed");
-  if (ob) HIP_TRY(hipMemcpy(dp->d_ops, dp->plan.ops.data(), ob, hipMemcpyHostToDevice));
-  if (!dp->plan.tables.empty())
-    HIP_TRY(hipMemcpy(dp->d_tab, dp->plan.tables.data(), dp->plan.tables.size() * 4, hipMemcpyHostToDevice));
-  *out = dp.get();
-  net->plans.emplace(std::move(key), std::move(dp));
+  DevPlan *dp = nullptr;
+  if (it != net->plans.end()) {
+    dp = it->second.get();
+  } else {
+    auto np = std::make_unique<DevPlan>();
+    tn::PlanArgs pa;
+    pa.slices = slices;
+    pa.chi = chi;
+    pa.env = env;
+    bool unsup = false;
+    std::string err = tn::make_plan(net->g, pa, np->plan, &unsup);
+    if (!err.empty()) return fail(unsup ? TN_EUNSUPPORTED : TN_EINVAL, err);
+    make_segments(*np);
+    dp = np.get();
+    net->plans.emplace(std::move(key), std::move(np));
+  }
+  if (device && !dp->d_ops) {
+    size_t ob = dp->plan.ops.size() * sizeof(tn::Op), tb = std::max<size_t>(1, dp->plan.tables.size()) * 4;
+    if (!dp->d_tab && hipMalloc(&dp->d_tab, tb) != hipSuccess) return fail(TN_ENOMEM, "device allocation for the plan failed");
+    if (!dp->plan.tables.empty())
+      HIP_TRY(hipMemcpy(dp->d_tab, dp->plan.tables.data(), dp->plan.tables.size() * 4, hipMemcpyHostToDevice));
+    tn::Op *ops = nullptr;                 // set last: a plan with d_ops has both copies
+    if (hipMalloc(&ops, std::max<size_t>(ob, 64)) != hipSuccess) return fail(TN_ENOMEM, "device allocation for the plan failed");
+    dp->d_ops = ops;
+    if (ob) HIP_TRY(hipMemcpy(dp->d_ops, dp->plan.ops.data(), ob, hipMemcpyHostToDevice));
+  }
+  *out = dp;
   return TN_OK;
 }
 
@@ -242,8 +253,8 @@ int launch_segments(tn_net net, DevPlan *dp, const tn::KeepParams &kp, hipStream
   for (const Seg &sg : dp->segs) {
     if (sg.kind == 0) HIP_TRY(tn::launch_interp_range(net->d_nd, sg.first, sg.last, kp, st));
     else if (sg.kind == 1)
-      HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, sg.blocks, kp.split, sg.piped, net->d_split, sg.split_blocks,
-                                   st));
+      HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, sg.blocks, tn::op_split(kp, dp->plan.ops[size_t(sg.first)].flags),
+                                   sg.piped, net->d_split, sg.split_blocks, st));
     else HIP_TRY(tn::launch_rescale_grid(net->d_nd, sg.first, sg.blocks, net->d_part, st));
   }
   return TN_OK;
@@ -259,7 +270,8 @@ int run_stepwise(tn_net net, DevPlan *dp, const tn::NetDev &nd, const tn::KeepPa
   if (kp.split) {                           // planes for the largest chip-wide GEMM of the plan
     int64_t need = 0;
     for (const Seg &sg : dp->segs)
-      if (sg.kind == 1) need = std::max(need, sg.split_bytes);
+      if (sg.kind == 1 && tn::op_split(kp, dp->plan.ops[size_t(sg.first)].flags))
+        need = std::max(need, sg.split_bytes);
     if (need > net->split_cap) {
       HIP_TRY(hipStreamSynchronize(st));    // earlier launches may still read the old planes
       if (net->d_split) (void)hipFree(net->d_split);
@@ -278,7 +290,8 @@ int run_stepwise(tn_net net, DevPlan *dp, const tn::NetDev &nd, const tn::KeepPa
   };
   put(&kp.tau_rel, 8); put(&kp.tau_deg, 8); put(&kp.floor, 8); put(&kp.residual_tol, 8);
   put(&kp.model, sizeof(kp.model)); put(&kp.hx, sizeof(kp.hx)); put(&kp.hy, sizeof(kp.hy));
-  put(&kp.hcount, sizeof(kp.hcount)); put(&kp.hcap, 8); put(&kp.split, 4); put(kp.gemm_cfg, 12);
+  put(&kp.hcount, sizeof(kp.hcount)); put(&kp.hcap, 8); put(&kp.split, 4); put(&kp.split_all, 4);
+  put(kp.gemm_cfg, 12);
   put(&net->d_split, sizeof(net->d_split));
   if (!dp->gexec || dp->gkey != key) {
     if (dp->gexec) { (void)hipGraphExecDestroy(dp->gexec); dp->gexec = nullptr; }
@@ -417,17 +430,10 @@ static int contract_batch(const tn_net *nets, const tn_path *paths, const int32_
                           const int32_t *env_sizes, int32_t n, const tn_options &o, const tn::KeepParams &kp,
                           tn_result *outs);
 
-int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int32_t *max_ranks,
-                             const int32_t *env_sizes, int32_t n, const tn_options *opt, tn_result *outs) {
-  g_err.clear();
-  if (!nets || !paths || !outs || !max_ranks || !env_sizes || n < 1) return fail(TN_EINVAL, "null arrays or empty batch");
-  for (int32_t i = 0; i < n; ++i) {
-    if (max_ranks[i] < 1) return fail(TN_EINVAL, "max_rank must be >= 1");
-    if (env_sizes[i] < 1) return fail(TN_EINVAL, "env_size must be >= 1");
-  }
-  tn_options o = opt ? *opt : defaults();
-  if (o.precision != TN_FP64 && o.precision != TN_SPLIT_BF16X3 && o.precision != TN_SPLIT_FP16X3)
-    return fail(TN_EINVAL, "unknown precision");
+// Options (NULL: defaults) checked and turned into the kernels' launch parameters.
+static int prepare_options(const tn_options *opt, tn_options &o, tn::KeepParams &kp_out) {
+  o = opt ? *opt : defaults();
+  if (o.precision < TN_FP64 || o.precision > TN_SPLIT_FP16X3_ALL) return fail(TN_EINVAL, "unknown precision");
   if (o.eig != TN_EIG_EXACT && o.eig != TN_EIG_LEARNED) return fail(TN_EINVAL, "unknown eigensolve mode");
   if (o.eig == TN_EIG_LEARNED && !o.model) return fail(TN_EINVAL, "learned eigensolve needs a model");
   if (o.eig == TN_EIG_LEARNED && !(o.residual_tol > 0)) return fail(TN_EINVAL, "residual_tol must be > 0");
@@ -436,10 +442,45 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int
     if (o.gemm_config[c] < 0 || o.gemm_config[c] > tn::kGemmConfigs) return fail(TN_EINVAL, "gemm_config out of range");
   tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
   kp.residual_tol = o.residual_tol;
-  kp.split = int(o.precision);
+  kp.split = o.precision == TN_FP64 ? 0 : (o.precision == TN_SPLIT_BF16X3 || o.precision == TN_SPLIT_BF16X3_ALL ? 1 : 2);
+  kp.split_all = o.precision == TN_SPLIT_BF16X3_ALL || o.precision == TN_SPLIT_FP16X3_ALL ? 1 : 0;
   for (int c = 0; c < 3; ++c) kp.gemm_cfg[c] = o.gemm_config[c];
   if (o.eig == TN_EIG_LEARNED) kp.model = o.model->d_w;
+  kp_out = kp;
+  return TN_OK;
+}
+
+int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths, const int32_t *max_ranks,
+                             const int32_t *env_sizes, int32_t n, const tn_options *opt, tn_result *outs) {
+  g_err.clear();
+  if (!nets || !paths || !outs || !max_ranks || !env_sizes || n < 1) return fail(TN_EINVAL, "null arrays or empty batch");
+  for (int32_t i = 0; i < n; ++i) {
+    if (max_ranks[i] < 1) return fail(TN_EINVAL, "max_rank must be >= 1");
+    if (env_sizes[i] < 1) return fail(TN_EINVAL, "env_size must be >= 1");
+  }
+  tn_options o;
+  tn::KeepParams kp{};
+  const int rc = prepare_options(opt, o, kp);
+  if (rc != TN_OK) return rc;
   return contract_batch(nets, paths, max_ranks, env_sizes, n, o, kp, outs);
+}
+
+static void fill_result(const tn::NetScalars &sc, const DevPlan &dp, double secs, tn_result &r) {
+  std::memset(&r, 0, sizeof(r));
+  if (sc.zero) {
+    r.log_abs = -std::numeric_limits<double>::infinity();
+    r.sign = 0;
+  } else {
+    r.log_abs = double(sc.exp_sum) * std::log(2.0) + sc.log_sum;
+    r.sign = int32_t(sc.sign);
+  }
+  r.seconds = secs;
+  r.flops = sc.flops;
+  r.eig_flops = sc.eig_flops;
+  r.n_eig = dp.plan.n_eig;
+  r.n_fallback = sc.n_fallback;
+  r.max_residual = sc.max_resid;
+  r.n_learned = sc.n_learned;
 }
 
 static int contract_batch(const tn_net *nets, const tn_path *paths, const int32_t *max_ranks,
@@ -465,22 +506,7 @@ static int contract_batch(const tn_net *nets, const tn_path *paths, const int32_
   if (rc != TN_OK) return rc;
   for (int32_t i = 0; i < n; ++i) {
     v[i]->last = sc[i];
-    tn_result &r = outs[i];
-    std::memset(&r, 0, sizeof(r));
-    if (sc[i].zero) {
-      r.log_abs = -std::numeric_limits<double>::infinity();
-      r.sign = 0;
-    } else {
-      r.log_abs = double(sc[i].exp_sum) * std::log(2.0) + sc[i].log_sum;
-      r.sign = int32_t(sc[i].sign);
-    }
-    r.seconds = secs;
-    r.flops = sc[i].flops;
-    r.eig_flops = sc[i].eig_flops;
-    r.n_eig = plans[i]->plan.n_eig;
-    r.n_fallback = sc[i].n_fallback;
-    r.max_residual = sc[i].max_resid;
-    r.n_learned = sc[i].n_learned;
+    fill_result(sc[i], *plans[i], secs, outs[i]);
   }
   return TN_OK;
 }
@@ -811,7 +837,9 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
   op.c = 0;
   std::vector<double> ws(int64_t(M) * N, 0.0);
   tn::KeepParams kp{1e-15, 1e-12, tn::kClusterFloor};
-  kp.split = precision;
+  if (precision < TN_FP64 || precision > TN_SPLIT_FP16X3_ALL) return fail(TN_EINVAL, "unknown precision");
+  kp.split = precision == TN_FP64 ? 0 : (precision == TN_SPLIT_BF16X3 || precision == TN_SPLIT_BF16X3_ALL ? 1 : 2);
+  kp.split_all = 1;                 // the diagnostic product is split whatever its class
   int blocks = 0;
   bool piped = false;
   if (chip_wide) {   // the launch the planner gives a chip-wide contraction of this shape

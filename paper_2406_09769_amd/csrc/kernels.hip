@@ -1607,7 +1607,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
       case OP_GEMM: {
         const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
         const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-        if (!gemm_op(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc, kp.split, kp.gemm_cfg))
+        if (!gemm_op(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc, op_split(kp, op.flags), kp.gemm_cfg))
           gemm_tiles_k<kKCache>(op, A, B, nd.ws + op.c, nd.tab, lds, 0, 1, nd.sc);
         break;
       }
@@ -2041,5 +2041,6 @@ hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, doub
                      (const double *)partial, blocks);
   return hipGetLastError();
 }
+
 
 }  // namespace tn

@@ -29,6 +29,8 @@ struct KeepParams {
   int *hcount;             // harvest: rows written so far (atomic)
   long long hcap;          // harvest: capacity in rows
   int split;               // contraction precision: 0 FP64, 1 BF16 x3 split, 2 FP16 x3 split
+  int split_all;           // split: 0 = only environment and density-matrix GEMMs (F_ENV),
+                           // 1 = every GEMM
   int gemm_cfg[3];         // FP64 GEMM block configuration for ops of <= 16, <= 32, > 32 rows:
                            // 0 = built-in choice, k = candidate k-1 of kGemmConfigs
 };
@@ -46,6 +48,11 @@ hipError_t launch_mlp_train(float *w, float *m, float *v, const float *X, const 
                             float *grad_out, hipStream_t stream);
 
 hipError_t launch_interp(const NetDev *nets_dev, int n_nets, const KeepParams &kp, hipStream_t stream);
+
+// Precision a GEMM op runs in under kp: kp.split for the ops the split applies to, else 0.
+__host__ __device__ inline int op_split(const KeepParams &kp, int32_t op_flags) {
+  return (kp.split && (kp.split_all || (op_flags & F_ENV))) ? kp.split : 0;
+}
 
 // Large networks, op by op: one workgroup over ops [first, last) of nd_dev's network;
 // one GEMM op or one RESCALE op over `blocks` workgroups (partial: blocks doubles of

@@ -137,6 +137,8 @@ class Builder {
   }
   int32_t n_dyn() const { return n_dyn_; }
   std::string err;
+  int32_t gemm_flags = 0;     // flags given to every GEMM emitted (F_ENV while environments
+                              // and density matrices are built)
 
   struct Group {
     std::vector<int64_t> lab, dim, sa, sb;   // labels, static dims, strides in A (and B)
@@ -303,6 +305,7 @@ class Builder {
     out.buf = new_buf(out.size());
     Op o{};
     o.kind = OP_GEMM;
+    o.flags = gemm_flags;
     o.am = make_map(ga.dim, ga.sa);
     o.bn = make_map(gb.dim, gb.sa);
     int64_t K = 1;
@@ -777,6 +780,7 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
 
     // right environments R_k, k = n-1 .. 2
     std::vector<Sym> R(n + 1);
+    B.gemm_flags = F_ENV;
     for (int64_t k = n - 1; k >= 2; --k) {
       int64_t lf = leaf[k];          // leaf of position k+1
       std::vector<Sym> ket = gsyms(k + 1), all = ket;
@@ -793,6 +797,7 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
       B.rescale(r, false);
       R[k] = r;
     }
+    B.gemm_flags = 0;
 
     // forward sweep
     std::vector<Sym> g12 = gsyms(1), g2 = gsyms(2);
@@ -815,10 +820,12 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
         *unsupported = true;
         return "density matrix of dimension " + std::to_string(nr) + " exceeds the supported 128";
       }
+      B.gemm_flags = F_ENV;
       Sym T = B.contract_ab(C, R[k]);            // rows x bra(X_k)
       Sym Cb = C;
       for (auto &l : Cb.lab) l = bra_of(l);      // C with every mode primed
       Sym L = B.contract_ab(T, Cb);              // rows x bra(rows)
+      B.gemm_flags = 0;
       int64_t ucols = std::min<int64_t>({int64_t(a.chi), nr, xdim(k)});
       int64_t bond = B.fresh();
       Sym U = B.eig(L, rows.size(), ucols, bond);

@@ -25,6 +25,9 @@ enum OpFlags : int32_t {
   F_A_KFAST = 8,      // load A tiles with k varying fastest across threads
   F_B_NFAST = 16,     // load B tiles with n varying fastest across threads
   F_V_GLOBAL = 32,    // OP_EIG: reflector scratch (2 (n*n + n) doubles) at .b
+  F_ENV = 64,         // OP_GEMM: builds a right environment or a density matrix; its
+                      // rounding only moves the kept subspaces, never the value carried
+                      // along the main chain (the split forms may run it in 16-bit parts)
 };
 
 // A two-level index map over a row-major multi-index: off(i) = hi[i / lo_n] + lo[i % lo_n]

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtnapprox.so")
 
 TN_OK, TN_EINVAL, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_EUNSUPPORTED = range(6)
-TN_FP64, TN_SPLIT_BF16X3, TN_SPLIT_FP16X3 = range(3)
+TN_FP64, TN_SPLIT_BF16X3, TN_SPLIT_FP16X3, TN_SPLIT_BF16X3_ALL, TN_SPLIT_FP16X3_ALL = range(5)
 TN_EIG_EXACT, TN_EIG_LEARNED = range(2)
 
 

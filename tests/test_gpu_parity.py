@@ -202,4 +202,4 @@ def test_chip_wide_network_replays_its_graph(T):
     d = T.tn_contract_approx(h, net.slices, 16, 1)
     assert a.log_abs == b.log_abs == d.log_abs and a.sign == b.sign == d.sign == s
     assert abs(a.log_abs - v) / net.n_sites <= TOL
-    assert abs(c.log_abs - v) / net.n_sites <= 1e-6 and c.log_abs != a.log_abs
+    assert abs(c.log_abs - v) / net.n_sites <= 1e-8 and c.log_abs != a.log_abs

@@ -1,12 +1,27 @@
 """The precision form (split BF16 x3 / FP16 x3 contractions, FP64 eigensolve) against
 the FP64 oracle.
 
-Stated per-result bound: |ln|Z|_form - ln|Z|_oracle| / N <= 1e-6. Each contraction of
-the form carries a relative error of at most 2^-20 of |A||B| (tested element by
-element in test_gpu_kernels.py); a step of the method normalises a product of a few
-such contractions, so its logarithm moves by O(2^-20) at most, and a network of N
-sites takes about N steps. Every error is printed; the measured worst case on the
-64x64 workload is two orders of magnitude inside the bound.
+The split forms TN_SPLIT_BF16X3 and TN_SPLIT_FP16X3 run only the contractions that
+build right environments and density matrices in 16-bit parts; the main chain that
+carries the value (projector application, the carried block, the closing
+contractions), the eigensolve and the log accumulation stay FP64. The value is then
+the FP64 contraction of the network with projectors onto slightly moved subspaces.
+
+What moves them: every 16-bit matrix instruction sums its products in FP32, so each
+density matrix carries an error of about 2^-24 of |C||R||C|^T, which for the positive
+Ising tensors is about 6e-8 ||L||. Eigen-directions of L whose eigenvalues lie below
+that level are noise in the split forms; kept directions at or below it are replaced by
+others of about the same weight, which changes the captured weight of each truncation
+at the 1e-8 level. Stated per-result bounds:
+* lattices whose kept spectra stay above the noise floor (the 2D and 3D lattices in
+  the disordered phase): |dlnZ|/N <= 1e-8, the accuracy the mixed form is measured at;
+* the 64x64 workload, whose near-critical networks keep eigenvalues down to 1e-15 of
+  the largest: |dlnZ|/N <= 3e-8 per result, and the count within 1e-8 is asserted;
+* networks whose cuts sit in a dense tail of the spectrum (the ordered 3D lattice at
+  beta 0.25, signed random graphs): |dlnZ|/N <= 1e-6, the same bound as the forms that
+  split every contraction (TN_SPLIT_*_ALL), whose main chain carries about 2^-20 of
+  relative rounding per step over about N steps.
+Every result is printed.
 """
 import json
 import os
@@ -17,7 +32,9 @@ from paper_2406_09769_amd import inputs
 from oracle import dm
 
 pytestmark = pytest.mark.gpu
-BOUND = 1e-6
+BOUND = 1e-8          # environment / density-matrix split on well-conditioned lattices
+BOUND_W2 = 3e-8       # the 64x64 workload (spectra kept down to the FP64 floor)
+BOUND_ILL = 1e-6      # cuts in a dense spectral tail; every contraction split
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -27,23 +44,28 @@ def T():
     return tnapprox
 
 
-@pytest.mark.parametrize("precision", [1, 2])
-@pytest.mark.parametrize("net_fn,chi,env", [
-    (lambda: inputs.ising_2d(6, 6, 0.44), 4, 1),
-    (lambda: inputs.ising_2d(6, 6, 0.44), 16, 1),
-    (lambda: inputs.ising_2d(16, 16, 0.44), 16, 2),
-    (lambda: inputs.ising_3d(4, 4, 4, 0.2217), 8, 1),
-    (lambda: inputs.ising_3d(5, 5, 5, 0.2217), 16, 1),     # chip-wide ops: per-chunk scaling
-    (lambda: inputs.ising_rrg(40, 1.0, 4100), 16, 1),
+def env_only(T, precision):
+    return precision in (T.TN_SPLIT_BF16X3, T.TN_SPLIT_FP16X3)
+
+
+@pytest.mark.parametrize("precision", [1, 2, 3, 4])
+@pytest.mark.parametrize("net_fn,chi,env,ill", [
+    (lambda: inputs.ising_2d(6, 6, 0.44), 4, 1, False),
+    (lambda: inputs.ising_2d(6, 6, 0.44), 16, 1, False),
+    (lambda: inputs.ising_2d(16, 16, 0.44), 16, 2, False),
+    (lambda: inputs.ising_3d(4, 4, 4, 0.2217), 8, 1, False),
+    (lambda: inputs.ising_3d(5, 5, 5, 0.2217), 16, 1, False),     # chip-wide ops: per-chunk scaling
+    (lambda: inputs.ising_rrg(40, 1.0, 4100), 16, 1, True),
 ])
-def test_precision_form_within_bound(T, precision, net_fn, chi, env):
+def test_precision_form_within_bound(T, precision, net_fn, chi, env, ill):
     net = net_fn()
     h = T.create_network(net)
     r = T.tn_contract_approx(h, net.slices, chi, env, precision=precision)
     v, s = dm.contract_approx(net, chi, env)
     d = abs(r.log_abs - v) / net.n_sites
-    print(f"{net.name} chi={chi} env={env} precision={precision}: |dlnZ|/N {d:.3e}", flush=True)
-    assert r.sign == s and d <= BOUND
+    bound = BOUND if env_only(T, precision) and not ill else BOUND_ILL
+    print(f"{net.name} chi={chi} env={env} precision={precision}: |dlnZ|/N {d:.3e} (bound {bound:.0e})", flush=True)
+    assert r.sign == s and d <= bound
 
 
 def test_fp64_unchanged_by_the_option(T):
@@ -54,11 +76,7 @@ def test_fp64_unchanged_by_the_option(T):
     assert a.log_abs == b.log_abs
 
 
-@pytest.mark.parametrize("tau_rel", [1e-15, 1e-10])
-@pytest.mark.parametrize("precision", [1, 2])
-def test_w2_full_size_precision_form(T, precision, tau_rel):
-    """All 32 networks of the 64x64 workload in one launch, with the default keep cutoff and
-    with the 1e-10 cutoff the split forms use in the benchmark."""
+def _w2(T):
     gold = json.load(open(os.path.join(HERE, "golden", "w2_oracle.json")))["rows"]
     nets, chis, envs, gl = [], [], [], []
     for chi, env in ((32, 1), (32, 2), (64, 1), (64, 2)):
@@ -67,13 +85,28 @@ def test_w2_full_size_precision_form(T, precision, tau_rel):
             chis.append(chi)
             envs.append(env)
             gl.append(next(x for x in gold if x["chi"] == chi and x["env"] == env and abs(x["beta"] - b) < 1e-12))
+    return nets, chis, envs, gl
+
+
+@pytest.mark.parametrize("tau_rel", [1e-15, 1e-10])
+@pytest.mark.parametrize("precision", [1, 2, 3])
+def test_w2_full_size_precision_form(T, precision, tau_rel):
+    """All 32 networks of the 64x64 workload in one launch, with the default keep cutoff and
+    with the 1e-10 cutoff the split forms use in the benchmark."""
+    nets, chis, envs, gl = _w2(T)
     hs = [T.create_network(n) for n in nets]
     rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], chis, envs, precision=precision, tau_rel=tau_rel)
     errs = [abs(r.log_abs - g["log_abs"]) / 4096 for r, g in zip(rs, gl)]
-    print(f"64x64 workload, precision={precision}, tau_rel={tau_rel:g}: kernel {rs[0].seconds:.3f} s, worst |dlnZ|/N {max(errs):.3e}, "
-          f"per (chi, env) group {[f'{max(errs[8 * i:8 * i + 8]):.1e}' for i in range(4)]}", flush=True)
+    within = sum(e <= BOUND for e in errs)
+    print(f"64x64 workload, precision={precision}, tau_rel={tau_rel:g}: kernel {rs[0].seconds:.3f} s, worst |dlnZ|/N "
+          f"{max(errs):.3e}, {within}/32 within 1e-8, per (chi, env) group "
+          f"{[f'{max(errs[8 * i:8 * i + 8]):.1e}' for i in range(4)]}", flush=True)
     assert all(r.sign == g["sign"] for r, g in zip(rs, gl))
-    assert max(errs) <= BOUND
+    if env_only(T, precision):
+        assert max(errs) <= BOUND_W2
+        assert within >= (30 if tau_rel < 1e-12 else 26)
+    else:
+        assert max(errs) <= BOUND_ILL
 
 
 @pytest.mark.parametrize("tau_rel", [1e-15, 1e-10])
@@ -90,5 +123,6 @@ def test_w3_full_size_precision_form(T, precision, tau_rel):
         print(f"W3 beta={g['beta']} chi={g['chi']} precision={precision} tau_rel={tau_rel:g}: |dlnZ|/N {d:.3e}, "
               f"{r.seconds:.2f} s",
               flush=True)
-        assert r.sign == g["sign"] and d <= BOUND
+        bound = BOUND if g["beta"] < 0.25 else BOUND_ILL     # beta 0.25: ordered phase
+        assert r.sign == g["sign"] and d <= bound
         del h
