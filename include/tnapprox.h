@@ -136,6 +136,24 @@ int tn_contract_approx_batch(const tn_net *nets, const tn_path *paths,
                              const int32_t *max_ranks, const int32_t *env_sizes, int32_t n,
                              const tn_options *opt, tn_result *outs);
 
+/* tn_contract_approx for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): it calls no
+ * hipMalloc, hipFree or allocating library routine. The op list, index tables,
+ * launch descriptor and workspace go into a static device array of 256 MiB that each
+ * GPU the library runs on holds from the library's load until the process ends (its
+ * address is looked up once per device, on the first call there). The network's
+ * tensors and result scalars are the handle's, allocated by tn_create; the plan is
+ * built on the host on first use and cached on the handle as usual.
+ * Same arguments, result and numbers as tn_contract_approx (the same kernels on the
+ * same op list; tn_result.seconds is host wall time of the launch here).
+ * TN_EUNSUPPORTED: the plan needs more than 256 MiB of scratch, or has contractions
+ * large enough to run over the whole chip (those need the grid scratch of the
+ * allocating entry point). Every call on a GPU shares that GPU's array, which keeps
+ * the last call's contents (nothing in it needs clearing: every op writes what later
+ * ops read); calls that overlap on one GPU, from any thread or stream, race. */
+int tn_contract_approx_noalloc(tn_net net, const tn_path *path, int32_t max_rank,
+                               int32_t env_size, const tn_options *opt, tn_result *out);
+
 /* ---------------------------------------------------------------- learned warm start
  * The learned eigensolve (TN_EIG_LEARNED) starts subspace iteration from the columns
  * of a density matrix L that a small MLP ranks highest, computed row by row from

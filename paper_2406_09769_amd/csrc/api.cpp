@@ -1,6 +1,7 @@
 // api.cpp - the C ABI (include/tnapprox.h): handles, plan cache, device buffers, launches.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -514,6 +515,60 @@ static int contract_batch(const tn_net *nets, const tn_path *paths, const int32_
 int tn_contract_approx(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size,
                        const tn_options *opt, tn_result *out) {
   return tn_contract_approx_batch(&net, path, &max_rank, &env_size, 1, opt, out);
+}
+
+int tn_contract_approx_noalloc(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size,
+                               const tn_options *opt, tn_result *out) {
+  g_err.clear();
+  if (!net || !out) return fail(TN_EINVAL, "null network handle or result");
+  if (max_rank < 1) return fail(TN_EINVAL, "max_rank must be >= 1");
+  if (env_size < 1) return fail(TN_EINVAL, "env_size must be >= 1");
+  tn_options o;
+  tn::KeepParams kp{};
+  int rc = prepare_options(opt, o, kp);
+  if (rc != TN_OK) return rc;
+  std::vector<std::vector<int32_t>> slices;
+  rc = read_path(path, net->g.nt, slices);
+  if (rc != TN_OK) return rc;
+  DevPlan *dp = nullptr;
+  rc = get_plan(net, slices, max_rank, env_size, &dp, /*device=*/false);
+  if (rc != TN_OK) return rc;
+  if (!dp->segs.empty())
+    return fail(TN_EUNSUPPORTED, "the allocation-free entry point runs networks that fit one workgroup's pass; "
+                                 "this plan has contractions that run over the whole chip");
+  // scratch layout: descriptor | op list | index tables | workspace, each 256-byte aligned
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t ob = int64_t(dp->plan.ops.size() * sizeof(tn::Op));
+  const int64_t tb = int64_t(dp->plan.tables.size()) * 4;
+  const int64_t wb = std::max<int64_t>(dp->plan.ws_size, 32) * 8;
+  const int64_t off_ops = up(sizeof(tn::NetDev)), off_tab = off_ops + up(ob), off_ws = off_tab + up(tb);
+  const int64_t total = off_ws + wb;
+  if (total > tn::kNoAllocScratchBytes)
+    return fail(TN_EUNSUPPORTED, "the plan needs " + std::to_string(total) + " bytes of device scratch; the "
+                                 "allocation-free entry point holds " + std::to_string(tn::kNoAllocScratchBytes));
+  char *base = nullptr;
+  HIP_TRY(tn::noalloc_scratch(&base));
+  double *ws = reinterpret_cast<double *>(base + off_ws);
+  tn::NetDev nd{reinterpret_cast<const tn::Op *>(base + off_ops), int64_t(dp->plan.ops.size()),
+                reinterpret_cast<const int32_t *>(base + off_tab), ws, net->d_const, net->d_sc,
+                reinterpret_cast<int32_t *>(ws + dp->plan.dyn_off)};
+  tn::NetScalars init{};
+  init.sign = 1;
+  hipStream_t st = reinterpret_cast<hipStream_t>(o.hip_stream);
+  // the workspace is not cleared: every op writes what a later op reads
+  if (ob) HIP_TRY(hipMemcpyAsync(base + off_ops, dp->plan.ops.data(), size_t(ob), hipMemcpyHostToDevice, st));
+  if (tb) HIP_TRY(hipMemcpyAsync(base + off_tab, dp->plan.tables.data(), size_t(tb), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(base, &nd, sizeof(nd), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(net->d_sc, &init, sizeof(init), hipMemcpyHostToDevice, st));
+  const auto t0 = std::chrono::steady_clock::now();
+  HIP_TRY(tn::launch_interp(reinterpret_cast<const tn::NetDev *>(base), 1, kp, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  tn::NetScalars sc{};
+  HIP_TRY(hipMemcpy(&sc, net->d_sc, sizeof(sc), hipMemcpyDeviceToHost));
+  net->last = sc;
+  fill_result(sc, *dp, secs, *out);
+  return TN_OK;
 }
 
 int tn_plan_json(const int64_t *dims_flat, const int32_t *orders, int32_t n_tensors, const tn_edge *edges,

@@ -19,6 +19,8 @@
 //   OP_IDENT    identity matrices of the identity insertion.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace tn {
@@ -2042,5 +2044,38 @@ hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, doub
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- allocation-free scratch
+//
+// Device memory of the allocation-free entry point: one array per device, held from the
+// module's load to the end of the process. Host code must never pass `scratch` itself
+// to a kernel or a copy (on the host the name is only a stand-in); it uses the device
+// address hipGetSymbolAddress returns, looked up once per device with that device
+// current and kept per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(char **ptr) {
+  *ptr = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 }  // namespace tn

@@ -77,4 +77,10 @@ hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int spl
                             unsigned short *planes, int split_blocks, hipStream_t stream);
 hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, double *partial, hipStream_t stream);
 
+// Scratch of the allocation-free entry point: a static device array of this many bytes
+// per device. noalloc_scratch gives its device address on the current device (looked
+// up once per device); no device memory is allocated.
+constexpr int64_t kNoAllocScratchBytes = int64_t(256) << 20;
+hipError_t noalloc_scratch(char **ptr);
+
 }  // namespace tn

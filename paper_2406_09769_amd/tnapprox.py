@@ -64,6 +64,8 @@ def _load():
         "tn_contract_approx": (C.c_int, [C.c_void_p, P(tn_path), C.c_int32, C.c_int32, P(tn_options), P(tn_result)]),
         "tn_contract_approx_batch": (C.c_int, [P(C.c_void_p), P(tn_path), P(C.c_int32), P(C.c_int32), C.c_int32,
                                               P(tn_options), P(tn_result)]),
+        "tn_contract_approx_noalloc": (C.c_int, [C.c_void_p, P(tn_path), C.c_int32, C.c_int32, P(tn_options),
+                                                P(tn_result)]),
         "tn_plan_json": (C.c_int, [P(C.c_int64), P(C.c_int32), C.c_int32, P(tn_edge), C.c_int32, P(tn_path),
                                    C.c_int32, C.c_char_p, P(C.c_int64)]),
         "tn_destroy": (None, [C.c_void_p]),
@@ -196,6 +198,15 @@ def tn_contract_approx(h: Handle, slices, max_rank: int, env_size: int, **opt) -
     o = _options(**opt)
     r = tn_result()
     _check(LIB.tn_contract_approx(h.ptr, C.byref(p.path), int(max_rank), int(env_size), C.byref(o), C.byref(r)))
+    return _result(r)
+
+
+def tn_contract_approx_noalloc(h: Handle, slices, max_rank: int, env_size: int, **opt) -> Result:
+    p = _PathArgs(slices)
+    o = _options(**opt)
+    r = tn_result()
+    _check(LIB.tn_contract_approx_noalloc(h.ptr, C.byref(p.path), int(max_rank), int(env_size), C.byref(o),
+                                          C.byref(r)))
     return _result(r)
 
 
