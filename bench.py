@@ -4,15 +4,20 @@
 Workload (one step): the 64x64 open 2D Ising lattice (J=1, h=0) at the 8 inverse
 temperatures linspace(0.30, 0.60, 8), each at max_rank chi in {32, 64} and
 env_size in {1, 2}: 32 networks, contracted in ONE persistent launch (one
-workgroup per network). Inputs are uploaded once before timing (tn_create).
+workgroup per network, replayed from a captured HIP graph). Inputs are uploaded
+once before timing (tn_create).
 
 Prints one JSON line: networks/s over the timed steps (plain FP64 method), the
 roofline of the interpreter kernel (algorithmic GEMM flops per launch over its
 HIP-event duration), the per-site error of every result against the stored oracle
-values, the same workload once in each other form (split BF16x3 / FP16x3
-contractions; learned warm start of the eigensolve with an MLP trained on the GPU
-beforehand) with its networks/s and worst error, and the CPU oracle timed on a
-bounded sample of the same workload.
+values, and the same workload in each other form, every form timed as the median
+of several launches: split BF16x3 / FP16x3 contractions of environments and density
+matrices, the learned warm start of the eigensolve (an MLP trained on the GPU
+beforehand on density matrices of the 6x6, 64x64 and 3D lattice workloads), and
+their combination, the mixed + batched + learned form. Each form reports how many
+of its results lie within 1e-8 per site of the oracle and its networks/s counting
+only those, next to plain FP64 at the same keep cutoff. The CPU oracle is timed on
+a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -30,11 +35,13 @@ PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 GROUPS = [(32, 1), (32, 2), (64, 1), (64, 2)]
 CUS = 256
+PEAK_16BIT_TFLOPS = 2500.0      # MI355X dense BF16 / FP16 matrix cores
 # HBM bytes per launch of interp_kernel on this workload: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-# (factors from a 256 MiB copy), from profiles/interp_kernel_w2_64x64_fp64_hbm.txt. Set to
-# None whenever the kernel changes until the counters are taken again.
-TRAFFIC_BYTES = 6.953e9
+# (factors from a 256 MiB copy), from profiles/interp_kernel_w2_64x64_fp64_hbm.txt. None
+# whenever the kernel has changed since the counters were taken.
+TRAFFIC_BYTES = None
 SPLIT_TAU_REL = 1e-10   # keep cutoff of the split-precision forms (relative to the largest eigenvalue)
+BOUND = 1e-8            # accuracy the forms are counted at (per site, against the oracle)
 
 
 def workload():
@@ -63,26 +70,40 @@ def golden_errors(results, chis, envs):
 
 
 def train_model(T):
-    """The warm-start MLP trained on rows the method harvests from small lattices."""
+    """The warm-start MLP trained on rows the method harvests from density matrices of the
+    6x6 lattice (chi 4 and 16), 64x64 lattices at two inverse temperatures that are not in
+    the timed set, and a 4x4x4 cubic lattice (the 3D workload's single-workgroup size)."""
     from paper_2406_09769_amd import inputs
-    ds = T.Dataset(400_000)
-    for (L, b, chi) in ((16, 0.35, 16), (16, 0.44, 16), (16, 0.5, 16), (20, 0.44, 24)):
-        net = inputs.ising_2d(L, L, b)
+    ds = T.Dataset(600_000)
+    for net, chi in ((inputs.ising_2d(6, 6, 0.44), 4), (inputs.ising_2d(6, 6, 0.44), 16),
+                     (inputs.ising_2d(64, 64, 0.40), 32), (inputs.ising_2d(64, 64, 0.50), 32),
+                     (inputs.ising_3d(4, 4, 4, 0.2217), 16)):
         T.tn_harvest(T.create_network(net), net.slices, chi, 1, ds)
     m = T.Model(seed=7)
     m.train(ds, steps=3000, batch=128, lr=3e-3, seed=11)
     return m
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(sample: int):
-    """The oracle, untuned, on `sample` networks of the same workload (host cores)."""
-    import numpy as np  # noqa: F401
+    """The oracle, untuned, on `sample` networks of the same workload (all host threads the
+    BLAS uses), and on one network with one thread."""
     from paper_2406_09769_amd import inputs
     from oracle import dm
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
     picks = []
     betas = inputs.w2_betas()
@@ -93,23 +114,49 @@ def cpu_baseline(sample: int):
     for chi, env, b in picks:
         dm.contract_approx(inputs.ising_2d(64, 64, b), chi, env)
     dt = time.perf_counter() - t0
-    return {"value": len(picks) / dt, "unit": "networks/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{len(picks)} of the 32 networks, one per (chi, env) in turn at betas "
-                      f"{sorted(set(round(p[2], 4) for p in picks))}; {dt:.1f} s on the host"}
+    out = {"value": len(picks) / dt, "unit": "networks/s", "cores": int(threads), "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"{len(picks)} of the 32 networks, one per (chi, env) in turn at betas "
+                     f"{sorted(set(round(p[2], 4) for p in picks))}; {dt:.1f} s on the host"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            dm.contract_approx(inputs.ising_2d(64, 64, betas[0]), 32, 2)
+            d1 = time.perf_counter() - t1
+        out["one_thread"] = {"value": 1.0 / d1, "unit": "networks/s",
+                             "sample": f"1 network (beta {betas[0]:g}, chi 32, env 2), {d1:.1f} s"}
+    return out
+
+
+def time_form(T, handles, slices, chis, envs, reps, **kw):
+    """Median wall time of `reps` launches of the batch (after one untimed launch)."""
+    import statistics
+    import torch
+    T.tn_contract_approx_batch(handles, slices, chis, envs, **kw)
+    walls, kern, rs = [], [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs = T.tn_contract_approx_batch(handles, slices, chis, envs, **kw)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t)
+        kern.append(rs[0].seconds)
+    return statistics.median(walls), statistics.median(kern), rs
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=8, help="networks timed in the CPU oracle (0 = skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the runs of the other forms")
+    ap.add_argument("--form-reps", type=int, default=5, help="timed launches per form (median)")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM block autotuner (built-in shapes)")
     ap.add_argument("--cubic", type=int, default=0, metavar="CHI",
                     help="only contract the 8x8x8 3D lattice (beta 0.2217, plane slices) once at max_rank CHI "
                          "and print its time (the chip-wide op path) and exit")
-    ap.add_argument("--cubic-precision", choices=["fp64", "bf16x3", "fp16x3"], default="fp64",
+    ap.add_argument("--cubic-precision", choices=["fp64", "bf16x3", "fp16x3", "bf16x3_all"], default="fp64",
                     help="contraction arithmetic of the --cubic run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a buffer of MIB MiB once on the GPU (calibrates HBM byte counters) and exit")
@@ -119,7 +166,8 @@ def main():
         from paper_2406_09769_amd import inputs, tnapprox as T
         net = inputs.ising_3d(8, 8, 8, 0.2217)
         h = T.create_network(net)
-        prec = {"fp64": T.TN_FP64, "bf16x3": T.TN_SPLIT_BF16X3, "fp16x3": T.TN_SPLIT_FP16X3}[args.cubic_precision]
+        prec = {"fp64": T.TN_FP64, "bf16x3": T.TN_SPLIT_BF16X3, "fp16x3": T.TN_SPLIT_FP16X3,
+                "bf16x3_all": T.TN_SPLIT_BF16X3_ALL}[args.cubic_precision]
         stats = T.tn_plan_stats(h, net.slices, args.cubic, 1)
         T.tn_contract_approx(h, net.slices, args.cubic, 1, precision=prec)   # plan, workspace, graph capture
         torch.cuda.synchronize()
@@ -193,30 +241,53 @@ def main():
     errs = golden_errors(rs, chis, envs)
 
     forms = {}
-    # the split forms drop eigenvalues below 1e-10 of the largest: the split products do not
-    # resolve them, and keeping their noise directions only raises the kept ranks (the worst
-    # error against the oracle is the same as with 1e-15); the last form is plain FP64 with the
-    # keep cutoff at 1e-12, the method's own speed / accuracy knob
+    # Every form runs the same 32 networks in one launch and is timed as the median of
+    # --form-reps launches. The split forms drop eigenvalues below 1e-10 of the largest: their
+    # 16-bit products resolve nothing below that (the FP32 sums inside each 16-bit matrix
+    # instruction leave about 6e-8 of ||L||), and plain FP64 at the same cutoff is timed beside
+    # them, so that the arithmetic is compared at equal method settings.
+    model = None if args.no_forms else train_model(T)
     form_list = [] if args.no_forms else [
-        ("split_bf16x3", lambda: dict(precision=T.TN_SPLIT_BF16X3, tau_rel=SPLIT_TAU_REL)),
-        ("split_fp16x3", lambda: dict(precision=T.TN_SPLIT_FP16X3, tau_rel=SPLIT_TAU_REL)),
-        ("learned_warm_start", lambda: dict(eig=T.TN_EIG_LEARNED, model=train_model(T))),
-        ("fp64_tau_rel_1e-12", lambda: dict(tau_rel=1e-12))]
-    for name, make_kw in form_list:
-        kw = make_kw()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        rf = T.tn_contract_approx_batch(handles, slices, chis, envs, stream=stream, **kw)
-        torch.cuda.synchronize()
-        dtf = time.perf_counter() - t1
+        ("fp64", dict()),
+        ("fp64_tau_rel_1e-10", dict(tau_rel=SPLIT_TAU_REL)),
+        ("split_bf16x3", dict(precision=T.TN_SPLIT_BF16X3, tau_rel=SPLIT_TAU_REL)),
+        ("split_fp16x3", dict(precision=T.TN_SPLIT_FP16X3, tau_rel=SPLIT_TAU_REL)),
+        ("split_bf16x3_all", dict(precision=T.TN_SPLIT_BF16X3_ALL, tau_rel=SPLIT_TAU_REL)),
+        ("learned_warm_start", dict(eig=T.TN_EIG_LEARNED, model=model)),
+        ("mixed_batched_learned", dict(precision=T.TN_SPLIT_BF16X3, tau_rel=SPLIT_TAU_REL, eig=T.TN_EIG_LEARNED,
+                                       model=model)),
+    ]
+    for name, kw in form_list:
+        wall, kern, rf = time_form(T, handles, slices, chis, envs, args.form_reps, stream=stream, **kw)
         ef = golden_errors(rf, chis, envs)
-        forms[name] = {"networks_per_s": round(len(nets) / dtf, 4), "kernel_ms": round(rf[0].seconds * 1e3, 3),
+        within = sum(e <= BOUND for e in ef) if ef else None
+        fl = sum(r.flops for r in rf)
+        sfl = sum(r.split_flops for r in rf)
+        forms[name] = {"networks_per_s": round(len(nets) / wall, 4), "median_wall_ms": round(wall * 1e3, 3),
+                       "kernel_ms": round(kern * 1e3, 3),
                        "max_dlnZ_per_site_vs_oracle": (max(ef) if ef else None),
-                       "within_1e-8": (sum(e <= 1e-8 for e in ef) if ef else None)}
-        if name.startswith("learned"):
+                       "within_1e-8": within,
+                       "networks_per_s_within_1e-8": (round(within / wall, 4) if ef else None),
+                       "gemm_flops": fl,
+                       "fp64_mfma_frac": round((fl - sfl) / kern / 1e12 / PEAK_FP64_TFLOPS, 8)}
+        if sfl:
+            # each split contraction issues six 16-bit products per FP64 one
+            forms[name]["split_flops"] = sfl
+            forms[name]["issued_16bit_mfma_flops"] = 6 * sfl
+            forms[name]["mfma_16bit_frac"] = round(6 * sfl / kern / 1e12 / PEAK_16BIT_TFLOPS, 9)
+        if kw.get("eig") == T.TN_EIG_LEARNED:
             forms[name]["warm_starts_accepted"] = sum(r.n_learned for r in rf)
             forms[name]["eigensolves"] = sum(r.n_eig for r in rf)
         print(f"[bench] form {name}: {json.dumps(forms[name])}", file=sys.stderr, flush=True)
+    metric_summary = None
+    if "mixed_batched_learned" in forms:
+        mx, fp = forms["mixed_batched_learned"], forms["fp64"]
+        metric_summary = {
+            "mixed_batched_learned_networks_per_s_within_1e-8": mx["networks_per_s_within_1e-8"],
+            "plain_fp64_networks_per_s_within_1e-8": fp["networks_per_s_within_1e-8"],
+            "ratio": round(mx["networks_per_s_within_1e-8"] / fp["networks_per_s_within_1e-8"], 4),
+            "mixed_mfma_16bit_frac": mx.get("mfma_16bit_frac"),
+            "plain_fp64_mfma_frac": fp["fp64_mfma_frac"]}
 
     line = {
         "metric": METRIC,
@@ -242,6 +313,7 @@ def main():
         "accuracy": {"max_dlnZ_per_site_vs_oracle": (max(errs) if errs else None),
                      "within_1e-8": (sum(e <= 1e-8 for e in errs) if errs else None)},
         "forms": forms,
+        "metric_summary": metric_summary,
         "gemm_blocks": {"config": gemm_config, "autotune": tune_report},
     }
     if args.cpu_sample > 0:

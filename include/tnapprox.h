@@ -83,14 +83,20 @@ typedef enum {
 typedef struct tn_model_s *tn_model;      /* warm-start MLP weights on the device */
 typedef struct tn_dataset_s *tn_dataset;  /* harvested (features, leverage) rows on the device */
 
-/* Options; pass NULL for the defaults (FP64, exact eigensolve, tau_rel = 1e-15,
- * tau_deg = 1e-12, the null stream). */
+/* Options; pass NULL for the defaults (FP64, exact eigensolve, tau_rel = 1e-12,
+ * tau_deg = 0.1, the null stream). The rank rule (leading_eigenvectors of Algorithm
+ * density_matrix_alg, which leaves ties and numerical zeros open): keep at most
+ * max_rank eigenvectors, drop eigenvalues <= tau_rel * w1, and never cut where the
+ * spectrum does not separate: while w_k - w_{k+1} <= tau_deg * w_k and w_{k+1} exceeds
+ * 0.1 * tau_rel * w1, the cut moves up by one. With the defaults every cut is fixed by
+ * FP64 arithmetic (a cut at relative gap g moves the result by about eps / g under the
+ * backward error of any FP64 eigensolver). */
 typedef struct {
   int32_t precision;      /* tn_precision */
   int32_t eig;            /* tn_eig_mode */
   double residual_tol;    /* learned mode: accepted max ||L x - theta x|| / theta_1 (1e-6) */
   double tau_rel;         /* eigenvalues <= tau_rel * w1 are dropped */
-  double tau_deg;         /* clusters with gap <= tau_deg * w1 are never split */
+  double tau_deg;         /* no cut where w_k - w_{k+1} <= tau_deg * w_k (see above) */
   void *hip_stream;       /* hipStream_t the work is queued on (NULL = null stream) */
   tn_model model;         /* learned mode: the MLP that ranks the warm-start columns */
   int32_t gemm_config[3]; /* FP64 contraction block shape for ops of <= 16, <= 32 and more
@@ -112,6 +118,8 @@ typedef struct {
   int64_t n_fallback;     /* keep() fallbacks (all eigenvalues below the floors) */
   double max_residual;    /* learned mode: largest accepted relative subspace residual */
   int64_t n_learned;      /* learned mode: density matrices solved by the warm start */
+  int64_t split_flops;    /* the part of flops run in 16-bit parts by a split form (each such
+                             contraction issues six 16-bit matrix products per FP64 one) */
 } tn_result;
 
 typedef struct tn_net_s *tn_net;
@@ -208,12 +216,15 @@ const char *tn_last_error(void);
  * Used by the kernel tests; each runs one device op of the contraction program on
  * host data (copied in and out) and blocks. */
 
-/* Plan statistics for (path, max_rank, env_size) on net: stats[0..7] = op count,
+/* Plan statistics for (path, max_rank, env_size) on net: stats[0..8] = op count,
  * index-table entries, workspace doubles, GEMM flops (sum 2mnk), eigensolver flops
- * (9 n^3 per density matrix), density matrices, largest density-matrix dimension,
- * ops run over the whole chip (in a network with an op whose output exceeds 2^21
- * elements: every contraction or rescaling with at least 2^13 output elements and every
- * contraction of at least 2^24 flops; a network with none runs in one workgroup's pass). */
+ * (9 n^3 per density matrix and 4 m c q per QR factorisation), density matrices,
+ * largest density-matrix dimension, ops run over the whole chip (in a network with an
+ * op whose output exceeds 2^21 elements: every contraction or rescaling with at least
+ * 2^13 output elements and every contraction of at least 2^24 flops; a network with none
+ * runs in one workgroup's pass), and vertices that take the QR-SVD branch of Algorithm
+ * density_matrix_alg (open size above the crossing size: C = Q R, the leading
+ * eigenvectors of R R_k R^T mapped back through Q, instead of forming C R_k C^T). */
 int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_size,
                   int64_t *stats);
 
@@ -246,8 +257,9 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, int32_t rest, const 
  * smaller than the matrix, every start column was dependent, the weight outside the
  * subspace could change the cut, or a Ritz residual was too large; entries 13-16 split
  * the time of the warm starts (accepted or not) into scoring and start basis, products
- * with L, the small eigensolve, and Ritz vectors with residuals (17 entries; times
- * measured by the first thread of the network's workgroup with the wall clock). */
+ * with L, the small eigensolve, and Ritz vectors with residuals; entry 17 is the time of
+ * the QR factorisations of the QR-SVD branch (18 entries; times measured by the first
+ * thread of the network's workgroup with the wall clock). */
 int tn_profile_last(tn_net net, double *seconds_by_kind);
 
 /* x <- x * 2^-e with e the frexp exponent of max|x|; returns e. */

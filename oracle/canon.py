@@ -25,7 +25,7 @@ import numpy as np
 
 from .dm import T, contract, absorb_all, absorb_in_order, closing_order, plan_partition, partitions_of
 
-CLUSTER_FLOOR = 1e-10
+CLUSTER_FLOOR = 0.1        # separation rule above CLUSTER_FLOOR * tau_rel * w1, as in dm.keep
 
 LN2 = math.log(2.0)
 
@@ -37,7 +37,7 @@ def _keep_from_spectrum(w, chi, tau_rel, tau_deg):
     k = min(chi, dim)
     while k >= 1 and w[k - 1] <= tau_rel * w1:
         k -= 1
-    while 1 <= k < dim and w[k] > CLUSTER_FLOOR * w1 and w[k - 1] - w[k] <= tau_deg * w1:
+    while 1 <= k < dim and w[k] > CLUSTER_FLOOR * tau_rel * w1 and w[k - 1] - w[k] <= tau_deg * w[k - 1]:
         k -= 1
     return k if k > 0 else min(chi, dim)
 
@@ -148,7 +148,7 @@ def _canon_sweep(plan, j, chi, tau_rel, tau_deg):
     return out, acc
 
 
-def contract_canon(net, chi: int, env_size: int, tau_rel=1e-15, tau_deg=1e-12):
+def contract_canon(net, chi: int, env_size: int, tau_rel=1e-12, tau_deg=0.1):
     """ln|Z|, sign(Z) by canonicalisation-based truncation on the oracle's plan."""
     path_index = {}
     for s in net.slices:

@@ -32,11 +32,19 @@ Readings of the paper that this file fixes (the paper leaves them open):
   MPS tensor sits at the new position of its own leaf (else likewise by its old
   position); a leaf whose owning tensor sits elsewhere is carried to its position
   by an identity matrix (the identity insertion of section 6.2);
-* keep(): top eigenpairs, at most chi, dropping eigenvalues <= tau_rel * w1
-  (tau_rel = 1e-15, the rounding floor of an FP64 eigensolve) and never cutting
-  inside a near-degenerate cluster (gap <= tau_deg * w1, tau_deg = 1e-12) whose
-  lower member exceeds CLUSTER_FLOOR * w1 = 1e-10 * w1 (a split below that floor
-  moves less than 1e-10 of the weight); the rule is blind to zero padding;
+* keep() (the paper's leading_eigenvectors says nothing about ties or numerical
+  zeros): top eigenpairs, at most chi, dropping eigenvalues <= tau_rel * w1
+  (tau_rel = 1e-12) and never cutting where the spectrum does not separate:
+  while w_k - w_{k+1} <= tau_deg * w_k (tau_deg = 0.1) and w_{k+1} exceeds
+  CLUSTER_FLOOR * tau_rel * w1 (CLUSTER_FLOOR = 0.1), the cut moves up by one.
+  Why: any backward-stable FP64 eigensolver returns the spectrum of L + E with
+  ||E|| up to a small multiple of eps ||L||. A cut at relative gap g turns the kept
+  subspace by about eps w1 / (g w_k) and moves the result by about eps / g, so
+  tau_deg = 0.1 keeps every cut's sensitivity near 1e-15; and an eigenvalue kept
+  at 1e-15 w1 is indistinguishable from E, its eigenvector a random direction of
+  the near-null space, which later partitions can amplify (on #CSP networks such a
+  direction moved lnZ by 1e-7 per variable), so tau_rel = 1e-12 keeps only
+  eigenvalues the FP64 solve resolves. The rule is blind to zero padding;
 * the first tree vertex holds positions 1 and 2 (the first non-leaf node of the
   MPS tree joins the first two leaves).
 """
@@ -48,9 +56,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 LN2 = math.log(2.0)
-TAU_REL = 1e-15
-TAU_DEG = 1e-12
-CLUSTER_FLOOR = 1e-10
+TAU_REL = 1e-12
+TAU_DEG = 0.1
+CLUSTER_FLOOR = 0.1        # the separation rule applies to w_{k+1} > CLUSTER_FLOOR * tau_rel * w1
 
 # The symmetric eigensolver keep() calls. Any backward-stable one gives an equally
 # valid result; swapping it (e.g. for LAPACK's relatively robust representation
@@ -155,9 +163,9 @@ def keep(L: np.ndarray, chi: int, tau_rel=TAU_REL, tau_deg=TAU_DEG):
 
     Returns (U, w, k, fallback) with U = the k leading eigenvectors, w all
     eigenvalues in descending order. k starts at min(chi, dim), drops eigenvalues
-    <= tau_rel*w1 (numerical zeros), then steps down while the cut would split a
-    near-degenerate cluster that carries weight (w_{k+1} > CLUSTER_FLOOR*w1 and
-    w_k - w_{k+1} <= tau_deg*w1). Zero rows and columns added to L only add
+    <= tau_rel*w1 (below what an FP64 solve resolves), then steps down while the
+    spectrum does not separate at the cut (w_{k+1} > CLUSTER_FLOOR*tau_rel*w1 and
+    w_k - w_{k+1} <= tau_deg*w_k). Zero rows and columns added to L only add
     eigenvalues below both floors, so they never change k. If nothing survives,
     min(chi, dim) vectors are kept and fallback is True.
     """
@@ -169,13 +177,28 @@ def keep(L: np.ndarray, chi: int, tau_rel=TAU_REL, tau_deg=TAU_DEG):
     k = min(chi, dim)
     while k >= 1 and w[k - 1] <= tau_rel * w1:
         k -= 1
-    while 1 <= k < dim and w[k] > CLUSTER_FLOOR * w1 and w[k - 1] - w[k] <= tau_deg * w1:
+    while 1 <= k < dim and w[k] > CLUSTER_FLOOR * tau_rel * w1 and w[k - 1] - w[k] <= tau_deg * w[k - 1]:
         k -= 1
     fallback = False
     if k == 0:
         k = min(chi, dim)
         fallback = True
     return v[:, :k], w, k, fallback
+
+
+def keep_qr_svd(C: np.ndarray, R: np.ndarray, chi: int, tau_rel=TAU_REL, tau_deg=TAU_DEG):
+    """The QR-SVD branch of Algorithm density_matrix_alg for a vertex whose open size
+    (rows of C) exceeds its crossing size (columns of C): instead of forming the
+    density matrix L = C R C^T, orthogonalise C = Q Rc, take the leading eigenvectors
+    of the small matrix Rc R Rc^T under keep(), and map them back through Q. L and
+    Rc R Rc^T share their nonzero spectrum (L = Q (Rc R Rc^T) Q^T), so the kept rank and
+    subspace are those of keep(L). Returns (U, w, k, fallback) like keep(), with w the
+    spectrum of the small matrix."""
+    Q, Rc = np.linalg.qr(C)                # reduced: Q has min(rows, cols) columns
+    M = Rc @ R @ Rc.T
+    M = 0.5 * (M + M.T)
+    Uh, w, k, fb = keep(M, chi, tau_rel, tau_deg)
+    return Q @ Uh, w, k, fb
 
 
 # ---------------------------------------------------------------- structural plan
@@ -371,6 +394,7 @@ class Stats:
     max_asym: float = 0.0      # max |L - L^T| / max|L| before symmetrisation
     min_ratio: float = 1.0     # min w_min / w_1 over all density matrices
     kept: list = field(default_factory=list)
+    dims: list = field(default_factory=list)   # (rows, crossing size) of every vertex's C
     plans: list = field(default_factory=list)
     harvest: list = field(default_factory=list)
 
@@ -380,12 +404,21 @@ def _bra(lab, leaf):
 
 
 def contract_approx(net, chi: int, env_size: int, tau_rel=TAU_REL, tau_deg=TAU_DEG,
-                    gauge_rng=None, stats: Stats | None = None, harvest=False):
+                    gauge_rng=None, stats: Stats | None = None, harvest=False, env_checkpoint=None,
+                    qr_svd=False):
     """Approximate ln|Z| and sign(Z) of a closed network (returns (log_abs, sign)).
 
     gauge_rng: if given, every kept basis U is rotated by a random orthogonal
     matrix (the result must not change: only span(U) matters).
     harvest: keep every (density matrix, kept rank) pair in stats.harvest.
+    env_checkpoint: None keeps every right environment of a partition step in
+    memory; an integer c keeps only every c-th one (and the lowest stretch) and
+    recomputes the others from the nearest kept one above when the forward sweep
+    reaches them. A memory schedule only: the same operations on the same operands,
+    so the result is bit-identical.
+    qr_svd: at every vertex whose open size exceeds its crossing size take the QR-SVD
+    branch of the algorithm (keep_qr_svd) instead of forming the density matrix; the
+    default forms it everywhere (same kept subspaces, up to rounding).
     """
     if chi < 1 or env_size < 1:
         raise ValueError("chi and env_size must be >= 1")
@@ -422,7 +455,8 @@ def contract_approx(net, chi: int, env_size: int, tau_rel=TAU_REL, tau_deg=TAU_D
                 return -math.inf, 0
             mps, leaves = [(root, 1)], list(plan.leaf_edges)
         else:
-            mps, extra = _dm_sweep(plan, j, chi, tau_rel, tau_deg, gauge_rng, stats, harvest)
+            mps, extra = _dm_sweep(plan, j, chi, tau_rel, tau_deg, gauge_rng, stats, harvest, env_checkpoint,
+                                   qr_svd)
             acc += extra
             leaves = list(plan.leaf_edges)
             if mps is None:
@@ -431,7 +465,7 @@ def contract_approx(net, chi: int, env_size: int, tau_rel=TAU_REL, tau_deg=TAU_D
     return acc, sgn
 
 
-def _dm_sweep(plan, j, chi, tau_rel, tau_deg, gauge_rng, stats, harvest):
+def _dm_sweep(plan, j, chi, tau_rel, tau_deg, gauge_rng, stats, harvest, env_checkpoint=None, qr_svd=False):
     """Algorithm density_matrix_alg on the MPS tree of one partition step.
 
     Right environments R_k (k = n-1 .. 2) are the memoised density matrices
@@ -443,18 +477,38 @@ def _dm_sweep(plan, j, chi, tau_rel, tau_deg, gauge_rng, stats, harvest):
     grp = lambda k: [plan.units[i].t for i in plan.groups[k - 1]]
     X = crossing_labels(plan)
 
-    # right environments, leaf of each absorbed group traced between ket and bra
-    R = {}
-    for k in range(n - 1, 1, -1):
+    def env(k, r_next):
+        """R_k from R_{k+1} (None for k = n-1): the group at k+1 absorbed ket then bra,
+        its leaf traced between them."""
         leaf = plan.leaves[k]          # leaf of position k+1
         ket = grp(k + 1)
         bra = [T(t.data, tuple(_bra(l, leaf) for l in t.labels)) for t in ket]
-        start = R.get(k + 1)
-        r = absorb_all(start, ket + bra)
+        r = absorb_all(r_next, ket + bra)
         want = tuple(X[k]) + tuple(('bra', l) for l in X[k])
         assert set(r.labels) == set(want), (r.labels, want)
         r, _ = rescale(r.transpose_to(want))
-        R[k] = r
+        return r
+
+    # right environments, k = n-1 down to 2; with a checkpoint interval c only R_k with
+    # (n-1-k) % c == 0 and the lowest stretch (reached first by the forward sweep) stay
+    R = {}
+    low = 2 + ((n - 3) % env_checkpoint if env_checkpoint else 0)
+    prev = None
+    for k in range(n - 1, 1, -1):
+        r = env(k, prev)
+        if env_checkpoint is None or (n - 1 - k) % env_checkpoint == 0 or k <= low:
+            R[k] = r
+        prev = r
+    prev = None
+
+    def env_at(k):
+        if k not in R:                 # recompute the stretch below the next kept R
+            top = min(i for i in R if i > k)
+            r = R[top]
+            for i in range(top - 1, k - 1, -1):
+                r = env(i, r)
+                R[i] = r
+        return R[k]
 
     acc = 0.0
     c = absorb_all(None, grp(1) + grp(2))
@@ -466,22 +520,29 @@ def _dm_sweep(plan, j, chi, tau_rel, tau_deg, gauge_rng, stats, harvest):
     for k in range(2, n):
         nr = int(np.prod([c.dim(l) for l in rows]))
         cm = c.data.reshape(nr, -1)
-        rk = R[k]
+        rk = env_at(k)
+        if env_checkpoint is not None:
+            del R[k]                   # the forward sweep never returns to it
         d = int(np.prod([rk.dim(l) for l in X[k]])) if X[k] else 1
         rm = rk.data.reshape(d, d)
-        L = cm @ rm @ cm.T
-        mx = float(np.max(np.abs(L))) if L.size else 0.0
-        if mx > 0:
-            stats.max_asym = max(stats.max_asym, float(np.max(np.abs(L - L.T))) / mx)
-        L = 0.5 * (L + L.T)
-        U, w, kk, fb = keep(L, chi, tau_rel, tau_deg)
+        if qr_svd and nr > d:
+            U, w, kk, fb = keep_qr_svd(cm, rm, chi, tau_rel, tau_deg)
+            L = None
+        else:
+            L = cm @ rm @ cm.T
+            mx = float(np.max(np.abs(L))) if L.size else 0.0
+            if mx > 0:
+                stats.max_asym = max(stats.max_asym, float(np.max(np.abs(L - L.T))) / mx)
+            L = 0.5 * (L + L.T)
+            U, w, kk, fb = keep(L, chi, tau_rel, tau_deg)
         stats.n_eig += 1
+        stats.dims.append((nr, d))
         stats.n_fallback += int(fb)
         stats.kept.append(kk)
         if w[0] > 0:
             stats.min_ratio = min(stats.min_ratio, float(w[-1] / w[0]))
-        if harvest:
-            stats.harvest.append((L.copy(), kk))
+        if harvest and L is not None:
+            stats.harvest.append((L.copy(), kk, nr, d))
         if gauge_rng is not None:
             q, _ = np.linalg.qr(gauge_rng.standard_normal((kk, kk)))
             U = U @ q

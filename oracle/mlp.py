@@ -166,12 +166,13 @@ def rank_rule(theta: np.ndarray, navail: int, n: int, chi: int, tau_rel: float, 
               floor: float) -> int:
     """The keep rule of the density-matrix step applied to descending values theta
     (navail of them) of a matrix of order n: at most chi, drop values <= tau_rel*theta_1,
-    never cut a near-degenerate cluster that carries weight."""
+    never cut where the values do not separate (theta_k - theta_{k+1} <= tau_deg*theta_k
+    with theta_{k+1} above floor*theta_1)."""
     w1 = theta[0]
     k = min(chi, n, navail)
     while k >= 1 and theta[k - 1] <= tau_rel * w1:
         k -= 1
-    while 1 <= k < navail and theta[k] > floor * w1 and theta[k - 1] - theta[k] <= tau_deg * w1:
+    while 1 <= k < navail and theta[k] > floor * w1 and theta[k - 1] - theta[k] <= tau_deg * theta[k - 1]:
         k -= 1
     return k
 
@@ -183,7 +184,7 @@ def subspace_size(n: int, chi: int, rest: int) -> int:
     return min((kprev if (rest > 0 and kprev < chi) else chi) + 4, n - 1)
 
 
-def learned_solve(L, w, chi, rest, residual_tol=1e-6, tau_rel=1e-15, tau_deg=1e-12, floor=1e-10, iters=3,
+def learned_solve(L, w, chi, rest, residual_tol=1e-6, tau_rel=1e-12, tau_deg=0.1, floor=1e-13, iters=3,
                   scores=None):
     """The learned solve of one density matrix, step by step.
 
@@ -196,7 +197,7 @@ def learned_solve(L, w, chi, rest, residual_tol=1e-6, tau_rel=1e-15, tau_deg=1e-
        b = min(t, f) with t = tr(L) - tr(H) and f = sqrt(max(0, ||L||^2 - 2||W||^2 +
        ||H||^2) + FRO_SLACK * ||L||^2) (Frobenius norms). Accept when the weight outside
        is negligible, t <= TAIL_REL * theta_1, or when b cannot move a cut that chi
-       decides (k = min(chi, n), b <= theta_k / 2 and b < theta_k - tau_deg*theta_1),
+       decides (k = min(chi, n), b <= theta_k / 2 and b < (1 - tau_deg) theta_k),
        and every kept Ritz pair has ||W y - theta V y|| <= residual_tol * theta_1.
        Else V <- orth_drop(W) and repeat.
 
@@ -238,7 +239,7 @@ def learned_solve(L, w, chi, rest, residual_tol=1e-6, tau_rel=1e-15, tau_deg=1e-
         ok = k >= 1 and th1 > 0
         if ok:
             thk = thp[k - 1]
-            ok = t <= TAIL_REL * th1 or (k == kmax and b <= 0.5 * thk and b < thk - tau_deg * th1)
+            ok = t <= TAIL_REL * th1 or (k == kmax and b <= 0.5 * thk and b < thk - tau_deg * thk)
         if ok:
             Xr = V @ Y[:, :k]
             R = W @ Y[:, :k] - Xr * th[:k]

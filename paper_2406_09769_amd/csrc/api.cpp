@@ -46,12 +46,12 @@ struct DevPlan {
   std::vector<Seg> segs;     // empty: the whole network fits one workgroup's pass
   tn::Op *d_ops = nullptr;
   int32_t *d_tab = nullptr;
-  // the launches of `segs`, captured once as a HIP graph, and what they were captured
-  // with (the launch parameters; the network's descriptor is read at run time)
-  hipGraphExec_t gexec = nullptr;
-  std::vector<char> gkey;
+  // the launches of `segs`, captured as a HIP graph once per set of launch parameters
+  // (keyed by them; the network's descriptor is read at run time). Graphs are kept, not
+  // re-captured, when a call switches between parameter sets.
+  std::map<std::vector<char>, hipGraphExec_t> gexecs;
   ~DevPlan() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto &kv : gexecs) (void)hipGraphExecDestroy(kv.second);
     if (d_ops) (void)hipFree(d_ops);
     if (d_tab) (void)hipFree(d_tab);
   }
@@ -237,17 +237,67 @@ int ensure_ws(tn_net net, int64_t doubles) {
   return TN_OK;
 }
 
+// Default rank rule: keep eigenvalues above 1e-12 of the largest (what an FP64 solve
+// resolves), never cut at a relative gap of 10% or less.
+constexpr double kTauRel = 1e-12, kTauDeg = 0.1;
+
 tn_options defaults() {
   tn_options o;
   std::memset(&o, 0, sizeof(o));
   o.precision = TN_FP64;
   o.eig = TN_EIG_EXACT;
   o.residual_tol = 1e-6;
-  o.tau_rel = 1e-15;
-  o.tau_deg = 1e-12;
+  o.tau_rel = kTauRel;
+  o.tau_deg = kTauDeg;
   o.hip_stream = nullptr;
   return o;
 }
+
+// The launch parameters as a byte key, field by field (no padding bytes).
+void key_put(std::vector<char> &key, const void *p, size_t b) {
+  const char *c = static_cast<const char *>(p);
+  key.insert(key.end(), c, c + b);
+}
+std::vector<char> kp_key(const tn::KeepParams &kp) {
+  std::vector<char> key;
+  key_put(key, &kp.tau_rel, 8); key_put(key, &kp.tau_deg, 8); key_put(key, &kp.floor, 8);
+  key_put(key, &kp.residual_tol, 8); key_put(key, &kp.model, sizeof(kp.model)); key_put(key, &kp.hx, sizeof(kp.hx));
+  key_put(key, &kp.hy, sizeof(kp.hy)); key_put(key, &kp.hcount, sizeof(kp.hcount)); key_put(key, &kp.hcap, 8);
+  key_put(key, &kp.split, 4); key_put(key, &kp.split_all, 4); key_put(key, kp.gemm_cfg, 12);
+  return key;
+}
+
+constexpr size_t kMaxGraphsPerPlan = 16;
+
+// Capture the launches `launch(cs)` makes on the private stream cs into an executable graph.
+template <class F>
+int capture(hipStream_t cs, F &&launch, hipGraphExec_t *out) {
+  *out = nullptr;
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  const int rc = launch(cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &graph);
+  if (rc != TN_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+  if (ec != hipSuccess) return fail(TN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+  const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) { *out = nullptr; return fail(TN_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ei)); }
+  return TN_OK;
+}
+
+// The persistent launch of a batch: its launch descriptors and its captured graphs, one set
+// per host thread and device (handles used on distinct threads never share them). A graph
+// holds the single interpreter launch, whose arguments are the descriptor buffer, the
+// network count and the launch parameters; the descriptors are copied in before each
+// launch, so one graph serves every batch of that size and those parameters. Kept until
+// the thread ends (not freed: HIP may already be shut down at process exit).
+struct BatchCtx {
+  tn::NetDev *d_nd = nullptr;
+  size_t cap = 0;
+  hipStream_t cap_stream = nullptr;
+  std::map<std::vector<char>, hipGraphExec_t> execs;
+};
+thread_local std::map<int, BatchCtx> g_batch;
 
 // The op launches of a network that runs op by op, on stream st.
 int launch_segments(tn_net net, DevPlan *dp, const tn::KeepParams &kp, hipStream_t st) {
@@ -284,31 +334,22 @@ int run_stepwise(tn_net net, DevPlan *dp, const tn::NetDev &nd, const tn::KeepPa
     }
   }
   HIP_TRY(hipMemcpyAsync(net->d_nd, &nd, sizeof(nd), hipMemcpyHostToDevice, st));
-  std::vector<char> key;                    // the launch parameters, field by field (no padding)
-  auto put = [&key](const void *p, size_t b) {
-    const char *c = static_cast<const char *>(p);
-    key.insert(key.end(), c, c + b);
-  };
-  put(&kp.tau_rel, 8); put(&kp.tau_deg, 8); put(&kp.floor, 8); put(&kp.residual_tol, 8);
-  put(&kp.model, sizeof(kp.model)); put(&kp.hx, sizeof(kp.hx)); put(&kp.hy, sizeof(kp.hy));
-  put(&kp.hcount, sizeof(kp.hcount)); put(&kp.hcap, 8); put(&kp.split, 4); put(&kp.split_all, 4);
-  put(kp.gemm_cfg, 12);
-  put(&net->d_split, sizeof(net->d_split));
-  if (!dp->gexec || dp->gkey != key) {
-    if (dp->gexec) { (void)hipGraphExecDestroy(dp->gexec); dp->gexec = nullptr; }
+  std::vector<char> key = kp_key(kp);
+  key_put(key, &net->d_split, sizeof(net->d_split));
+  auto it = dp->gexecs.find(key);
+  if (it == dp->gexecs.end()) {
+    if (dp->gexecs.size() >= kMaxGraphsPerPlan) {   // bounded cache: earlier launches have completed
+      HIP_TRY(hipStreamSynchronize(st));
+      for (auto &kv : dp->gexecs) (void)hipGraphExecDestroy(kv.second);
+      dp->gexecs.clear();
+    }
     if (!net->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking));
-    HIP_TRY(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = launch_segments(net, dp, kp, net->cap_stream);
-    hipGraph_t graph = nullptr;
-    const hipError_t ec = hipStreamEndCapture(net->cap_stream, &graph);
-    if (rc != TN_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
-    if (ec != hipSuccess) return fail(TN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
-    const hipError_t ei = hipGraphInstantiate(&dp->gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ei != hipSuccess) { dp->gexec = nullptr; return fail(TN_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ei)); }
-    dp->gkey = key;
+    hipGraphExec_t ge = nullptr;
+    const int rc = capture(net->cap_stream, [&](hipStream_t cs) { return launch_segments(net, dp, kp, cs); }, &ge);
+    if (rc != TN_OK) return rc;
+    it = dp->gexecs.emplace(std::move(key), ge).first;
   }
-  HIP_TRY(hipGraphLaunch(dp->gexec, st));
+  HIP_TRY(hipGraphLaunch(it->second, st));
   return TN_OK;
 }
 
@@ -339,27 +380,68 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
     nd[q].sc = nets[i]->d_sc;
     nd[q].dyn = reinterpret_cast<int32_t *>(nets[i]->d_ws + plans[i]->plan.dyn_off);
   }
-  tn::NetDev *d_nd = nullptr;
-  if (n_persist > 0 && hipMalloc(&d_nd, n_persist * sizeof(tn::NetDev)) != hipSuccess)
-    return fail(TN_ENOMEM, "launch descriptor allocation failed");
-  std::unique_ptr<tn::NetDev, void (*)(tn::NetDev *)> guard(d_nd, [](tn::NetDev *p) { if (p) (void)hipFree(p); });
-  if (n_persist > 0)
-    HIP_TRY(hipMemcpyAsync(d_nd, nd.data(), n_persist * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  HIP_TRY(hipEventRecord(e0, st));
-  if (n_persist > 0) HIP_TRY(tn::launch_interp(d_nd, int(n_persist), kp, st));
+  hipGraphExec_t persist = nullptr;
+  if (n_persist > 0) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    BatchCtx &bc = g_batch[dev];
+    if (bc.cap < n_persist) {               // grow: graphs refer to the old buffer
+      HIP_TRY(hipStreamSynchronize(st));
+      for (auto &kv : bc.execs) (void)hipGraphExecDestroy(kv.second);
+      bc.execs.clear();
+      if (bc.d_nd) (void)hipFree(bc.d_nd);
+      bc.d_nd = nullptr;
+      bc.cap = 0;
+      const size_t cap = std::max<size_t>(n_persist, 64);
+      if (hipMalloc(&bc.d_nd, cap * sizeof(tn::NetDev)) != hipSuccess)
+        return fail(TN_ENOMEM, "launch descriptor allocation failed");
+      bc.cap = cap;
+    }
+    std::vector<char> key = kp_key(kp);
+    const int np = int(n_persist);
+    key_put(key, &np, sizeof(np));
+    auto it = bc.execs.find(key);
+    if (it == bc.execs.end()) {
+      if (bc.execs.size() >= kMaxGraphsPerPlan) {
+        HIP_TRY(hipStreamSynchronize(st));
+        for (auto &kv : bc.execs) (void)hipGraphExecDestroy(kv.second);
+        bc.execs.clear();
+      }
+      if (!bc.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&bc.cap_stream, hipStreamNonBlocking));
+      hipGraphExec_t ge = nullptr;
+      tn::NetDev *d_nd = bc.d_nd;
+      const int rc = capture(bc.cap_stream, [&](hipStream_t cs) -> int {
+        HIP_TRY(tn::launch_interp(d_nd, np, kp, cs));
+        return TN_OK;
+      }, &ge);
+      if (rc != TN_OK) return rc;
+      it = bc.execs.emplace(std::move(key), ge).first;
+    }
+    persist = it->second;
+    HIP_TRY(hipMemcpyAsync(bc.d_nd, nd.data(), n_persist * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
+  }
+  struct Events {                          // released on every return path
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  HIP_TRY(hipEventCreate(&ev.e0));
+  HIP_TRY(hipEventCreate(&ev.e1));
+  HIP_TRY(hipEventRecord(ev.e0, st));
+  if (persist) HIP_TRY(hipGraphLaunch(persist, st));
   for (size_t q = n_persist; q < n; ++q) {
     const int rc = run_stepwise(nets[order[q]], plans[order[q]], nd[q], kp, st);
-    if (rc != TN_OK) return rc;
+    if (rc != TN_OK) {
+      (void)hipStreamSynchronize(st);      // copies from this call's host buffers may be pending
+      return rc;
+    }
   }
-  HIP_TRY(hipEventRecord(e1, st));
-  HIP_TRY(hipEventSynchronize(e1));
+  HIP_TRY(hipEventRecord(ev.e1, st));
+  HIP_TRY(hipEventSynchronize(ev.e1));
   float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
   *seconds = ms * 1e-3;
   sc_out.resize(n);
   for (size_t i = 0; i < n; ++i)
@@ -441,7 +523,7 @@ static int prepare_options(const tn_options *opt, tn_options &o, tn::KeepParams 
   if (!(o.tau_rel >= 0) || !(o.tau_deg >= 0)) return fail(TN_EINVAL, "tau_rel and tau_deg must be >= 0");
   for (int c = 0; c < 3; ++c)
     if (o.gemm_config[c] < 0 || o.gemm_config[c] > tn::kGemmConfigs) return fail(TN_EINVAL, "gemm_config out of range");
-  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
+  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor * o.tau_rel};
   kp.residual_tol = o.residual_tol;
   kp.split = o.precision == TN_FP64 ? 0 : (o.precision == TN_SPLIT_BF16X3 || o.precision == TN_SPLIT_BF16X3_ALL ? 1 : 2);
   kp.split_all = o.precision == TN_SPLIT_BF16X3_ALL || o.precision == TN_SPLIT_FP16X3_ALL ? 1 : 0;
@@ -482,6 +564,7 @@ static void fill_result(const tn::NetScalars &sc, const DevPlan &dp, double secs
   r.n_fallback = sc.n_fallback;
   r.max_residual = sc.max_resid;
   r.n_learned = sc.n_learned;
+  r.split_flops = sc.split_flops;
 }
 
 static int contract_batch(const tn_net *nets, const tn_path *paths, const int32_t *max_ranks,
@@ -744,7 +827,7 @@ int tn_harvest(tn_net net, const tn_path *path, int32_t max_rank, int32_t env_si
   if (!net || !ds || !out) return fail(TN_EINVAL, "null arguments");
   if (max_rank < 1 || env_size < 1) return fail(TN_EINVAL, "max_rank and env_size must be >= 1");
   tn_options o = defaults();
-  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
+  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor * o.tau_rel};
   kp.hx = ds->d_x;
   kp.hy = ds->d_y;
   kp.hcount = ds->d_count;
@@ -773,6 +856,7 @@ int tn_plan_stats(tn_net net, const tn_path *path, int32_t max_rank, int32_t env
   int64_t grid_ops = 0;
   for (const Seg &sg : dp->segs) grid_ops += sg.kind != 0 ? 1 : 0;
   stats[7] = grid_ops;
+  stats[8] = dp->plan.n_qr;
   return TN_OK;
 }
 
@@ -787,6 +871,7 @@ int tn_profile_last(tn_net net, double *seconds_by_kind) {
   for (int r = 0; r < 4; ++r) seconds_by_kind[9 + r] = double(net->last.rej[r]);
   for (int r = 0; r < 4; ++r)
     seconds_by_kind[13 + r] = khz > 0 ? double(net->last.lticks[r]) / (double(khz) * 1e3) : 0.0;
+  seconds_by_kind[17] = khz > 0 ? double(net->last.qr_ticks) / (double(khz) * 1e3) : 0.0;
   return TN_OK;
 }
 
@@ -891,7 +976,7 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
   cst.insert(cst.end(), B, B + maxb);
   op.c = 0;
   std::vector<double> ws(int64_t(M) * N, 0.0);
-  tn::KeepParams kp{1e-15, 1e-12, tn::kClusterFloor};
+  tn::KeepParams kp{kTauRel, kTauDeg, tn::kClusterFloor * kTauRel};
   if (precision < TN_FP64 || precision > TN_SPLIT_FP16X3_ALL) return fail(TN_EINVAL, "unknown precision");
   kp.split = precision == TN_FP64 ? 0 : (precision == TN_SPLIT_BF16X3 || precision == TN_SPLIT_BF16X3_ALL ? 1 : 2);
   kp.split_all = 1;                 // the diagnostic product is split whatever its class
@@ -931,7 +1016,7 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, int32_t rest, const 
   op.flags |= tn::F_V_GLOBAL;
   std::vector<double> ws(lsz + usz + 2 * (np * np + np), 0.0);
   std::memcpy(ws.data(), L, size_t(n) * n * 8);
-  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor};
+  tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor * o.tau_rel};
   if (o.eig == TN_EIG_LEARNED) {
     kp.model = o.model->d_w;
     kp.residual_tol = o.residual_tol;
@@ -965,7 +1050,7 @@ int tn_debug_rescale(double *x, int64_t count, int64_t *exponent) {
   op.bm = tn::Box{0, int32_t(count), {0}, {0}};
   op.bnb = tn::Box{0, 1, {0}, {0}};
   std::vector<double> ws(x, x + count);
-  tn::KeepParams kp{1e-15, 1e-12, tn::kClusterFloor};
+  tn::KeepParams kp{kTauRel, kTauDeg, tn::kClusterFloor * kTauRel};
   tn::NetScalars sc{};
   int rc = run_single({op}, {}, ws, {}, kp, &sc);
   if (rc != TN_OK) return rc;

@@ -528,7 +528,10 @@ __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double
   int32_t *kA = reinterpret_cast<int32_t *>(lds + kPipedTiles);
   int32_t *kB = kA + K, *rA = kB + K, *rC = rA + M, *cB = rC + M, *cC = cB + N;
   const int tid = threadIdx.x;
-  if (tid == 0) sc->flops += 2LL * M * N * K;
+  if (tid == 0) {
+    sc->flops += 2LL * M * N * K;
+    if (split) sc->split_flops += 2LL * M * N * K;
+  }
   for (int k = tid; k < K; k += kThreads) {
     const int ks = box_conv(op.bk_, k);
     kA[k] = tab[op.ak + ks];
@@ -857,6 +860,63 @@ __device__ __forceinline__ ChaseOut ql_chase(Pair *de_, Pair *rb_, Pair *spare_,
   return o;
 }
 
+// Householder reduction of an order-n matrix (n <= kWaveReduceMax) by wave 0 alone: lane
+// r owns row j+1+r of the trailing block, so no column needs a workgroup barrier. A wave's
+// LDS accesses complete in order; the block-scope fences between the phases only keep
+// the compiler from moving loads above the stores they read. Same outputs as the
+// four-wave reduction: (d, e) in E.dd / E.ee, reflectors and betas in E.hv.
+constexpr int kWaveReduceMax = 64;
+__device__ void tri_reduce_wave(const EigWs &E) {
+  const int n = E.n, pa = E.pa, lane = threadIdx.x & 63;
+  double *A = E.A, *vv = E.vv, *pp = E.pp, *dd = E.dd, *ee = E.ee, *hv = E.hv;
+  for (int j = 0; j + 2 < n; ++j) {
+    const int m = n - j - 1;
+    const bool act = lane < m;
+    double *row = A + (j + 1 + lane) * pa + j + 1;       // lane's row of the trailing block
+    const double x = act ? row[-1] : 0.0;                 // column j below the diagonal
+    const double nrm2 = wave_sum(x * x);
+    const double x0 = __shfl(x, 0, 64);
+    if (nrm2 == 0.0) {                                    // column already reduced
+      if (lane == 0) { dd[j] = A[j * pa + j]; ee[j] = 0.0; hv[int64_t(n) * n + j] = 0.0; }
+      continue;
+    }
+    const double alpha = -copysign(sqrt(nrm2), x0);
+    const double beta = 1.0 / (nrm2 - x0 * alpha);        // 2 / (v^T v)
+    const double v = lane == 0 ? x0 - alpha : x;
+    if (act) { vv[lane] = v; hv[int64_t(j) * n + lane] = v; }
+    if (lane == 0) { dd[j] = A[j * pa + j]; ee[j] = alpha; hv[int64_t(n) * n + j] = beta; }
+    __threadfence_block();
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;        // p = beta * A_t v, row by row
+    if (act) {
+      int k = 0;
+      for (; k + 3 < m; k += 4) {
+        a0 = fma(row[k], vv[k], a0);
+        a1 = fma(row[k + 1], vv[k + 1], a1);
+        a2 = fma(row[k + 2], vv[k + 2], a2);
+        a3 = fma(row[k + 3], vv[k + 3], a3);
+      }
+      for (; k < m; ++k) a0 = fma(row[k], vv[k], a0);
+    }
+    const double p = beta * ((a0 + a1) + (a2 + a3));
+    if (act) pp[lane] = p;
+    const double K2 = beta * wave_sum(act ? v * p : 0.0);   // 2K = beta v^T p
+    __threadfence_block();
+    if (act) {                                            // A_t -= v p^T + p v^T - 2K v v^T
+      const double vk = v * K2;
+      for (int b = 0; b < m; ++b) row[b] -= fma(v, pp[b], fma(p, vv[b], -vk * vv[b]));
+    }
+    __threadfence_block();
+  }
+  if (lane == 0) {
+    if (n >= 2) {
+      dd[n - 2] = A[(n - 2) * pa + n - 2];
+      ee[n - 2] = A[(n - 1) * pa + n - 2];
+    }
+    dd[n - 1] = A[(n - 1) * pa + n - 1];
+    ee[n - 1] = 0.0;
+  }
+}
+
 __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
   const int n = E.n, pa = E.pa, tid = threadIdx.x, wave = tid >> 6;
   double *A = E.A, *vv = E.vv, *pp = E.pp, *ww = E.ww, *dd = E.dd, *ee = E.ee, *hv = E.hv;
@@ -868,6 +928,9 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
   const int lane = tid & 63, sub = tid & 3, grp = tid >> 2;
   double *rs = E.wq, *rs2 = E.wq + 4;                  // per-wave partial sums (free until QL)
   bool have_norm = false;
+  if (n <= kWaveReduceMax) {
+    if (wave == 0) tri_reduce_wave(E);
+  } else {
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;
     double nrm2;
@@ -946,6 +1009,7 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
     }
     dd[n - 1] = A[(n - 1) * pa + n - 1];
     ee[n - 1] = 0.0;
+  }
   }
   __syncthreads();
   if (timed && tid == 0) { const long long t = wall_clock64(); sc->ticks[0] += t - tph; tph = t; }
@@ -1083,14 +1147,16 @@ __device__ void order_desc(const EigWs &E) {
 }
 
 // The rank rule on descending eigenvalues w[0..navail) of a matrix of order n:
-// at most ucols, drop w <= tau_rel*w1, never split a cluster (gap <= tau_deg*w1)
-// whose lower member exceeds floor*w1. Returns 0 if nothing survives.
+// at most ucols, drop w <= tau_rel*w1 (below what the FP64 solve resolves), and never
+// cut where the spectrum does not separate: while w_k - w_{k+1} <= tau_deg*w_k and
+// w_{k+1} > floor*w1, the cut moves up (a cut at relative gap g moves the kept subspace
+// by about eps/g under the solver's backward error). Returns 0 if nothing survives.
 __device__ int keep_rank(const double *w, int navail, int n, int ucols, const KeepParams &kp) {
   const double w1 = w[0];
   int k = ucols < n ? ucols : n;
   if (k > navail) k = navail;
   while (k >= 1 && w[k - 1] <= kp.tau_rel * w1) --k;
-  while (k >= 1 && k < navail && w[k] > kp.floor * w1 && w[k - 1] - w[k] <= kp.tau_deg * w1) --k;
+  while (k >= 1 && k < navail && w[k] > kp.floor * w1 && w[k - 1] - w[k] <= kp.tau_deg * w[k - 1]) --k;
   return k;
 }
 
@@ -1103,6 +1169,33 @@ __device__ int keep_rank(const double *w, int navail, int n, int ucols, const Ke
 // thread and z_t -= V (T w_t), while the next block's V is staged into the other buffer.
 // Two barriers per four reflectors.
 constexpr int kWY = 4;
+// For up to 64 kept columns: 4 lanes per column (a quad of one wave) each take every 4th
+// row and add their dot products across the quad, one reflector at a time, so no step
+// waits on a workgroup barrier (the quads are independent; the reflectors are read only).
+__device__ void back_transform_quads(const EigWs &E, int k) {
+  const int n = E.n, tid = threadIdx.x, sub = tid & 3, t = tid >> 2;
+  if (t < k) {                               // every lane of the quad takes this branch
+    double *z = E.A + E.isrt[t] * n;
+    for (int j = n - 3; j >= 0; --j) {
+      const double beta = E.hv[int64_t(n) * n + j];
+      if (beta == 0.0) continue;             // the same j and beta in every lane
+      const int m = n - j - 1;
+      const double *v = E.hv + int64_t(j) * n;
+      double *zz = z + j + 1;
+      double a0 = 0.0, a1 = 0.0;
+      int i = sub;
+      for (; i + 4 < m; i += 8) {
+        a0 = fma(v[i], zz[i], a0);
+        a1 = fma(v[i + 4], zz[i + 4], a1);
+      }
+      if (i < m) a0 = fma(v[i], zz[i], a0);
+      const double w = beta * quad_sum(a0 + a1);
+      for (int r = sub; r < m; r += 4) zz[r] = fma(-w, v[r], zz[r]);
+    }
+  }
+  __syncthreads();
+}
+
 __device__ void back_transform(const EigWs &E, int k) {
   const int n = E.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, sub = tid & 3, grp = tid >> 2;
   double *Z = E.A;
@@ -1333,7 +1426,7 @@ __device__ void sym_times(const double *A, int pa, const double *V, int n, int p
 // the 2x2 block split; the slack covers their rounding). The result is accepted when
 //  * the weight off span(V) is negligible, t <= kLearnedTail * theta_1, or the rank is
 //    capped by max_rank and b cannot move that cut (b <= theta_k / 2 and
-//    b < theta_k - tau_deg * theta_1), and
+//    b < (1 - tau_deg) theta_k), and
 //  * every kept Ritz pair has ||L x - theta x|| <= residual_tol * theta_1.
 // Returns true with U written and the kept rank set; false leaves everything for the
 // exact solve (the reason is counted in sc->rej).
@@ -1436,7 +1529,7 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
     bool cut_ok = k >= 1 && th1 > 0.0;
     if (cut_ok) {
       const double thk = E.wsrt[k - 1];
-      cut_ok = tail <= kLearnedTail * th1 || (k == kmax && bnd <= 0.5 * thk && bnd < thk - kp.tau_deg * th1);
+      cut_ok = tail <= kLearnedTail * th1 || (k == kmax && bnd <= 0.5 * thk && bnd < thk - kp.tau_deg * thk);
     }
     if (cut_ok) {
       back_transform(E, k);                              // Y columns (p x k) in E.A
@@ -1513,7 +1606,8 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
   const int n = box_eff(op.bm);            // runtime dimension: the valid leading block
   const int ucols = op.K;
   const int tid = threadIdx.x;
-  if (kp.model && eig_learned(op, ws, dyn, kp, sc, lds, n, ld, ucols)) return;
+  const bool warm = !(op.flags & F_NO_WARM);
+  if (kp.model && warm && eig_learned(op, ws, dyn, kp, sc, lds, n, ld, ucols)) return;
   // the reflectors stay in LDS when they fit beside the work area (n up to about 90): the
   // reduction's writes and the back-transformation's reads then never wait on memory
   const bool hv_lds = eig_lds_doubles(n) + n * n + n <= kLdsDoubles;
@@ -1540,15 +1634,102 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
   }
   __syncthreads();
   const int k = E.flag[1];
-  back_transform(E, k);
+  if (k <= kThreads / 4) back_transform_quads(E, k);
+  else back_transform(E, k);
   double *U = ws + op.c;                  // U[j][i], j < k kept vectors, i < n components
   for (int e = tid; e < n * k; e += kThreads) {
     const int j = e / n, i = e % n;
     U[int64_t(j) * ld + i] = E.A[E.isrt[j] * n + i];
   }
   __syncthreads();
-  if (kp.hx) harvest_rows(op, ws, n, ld, k, kp, E.red, E.flag + 2);
+  if (kp.hx && warm) harvest_rows(op, ws, n, ld, k, kp, E.red, E.flag + 2);
   if (tid == 0) sc->ticks[7] += wall_clock64() - t0;
+}
+
+// ---------------------------------------------------------------- QR of the QR-SVD branch
+//
+// C (m x c valid, read through the op's row and column maps) = Q R by Householder
+// reflectors, one workgroup. C sits in LDS (odd pitch); quad t of the workgroup (4 lanes of
+// one wave) owns column t (c <= 64). Column j: quad j forms the reflector of rows j..m-1
+// (beta = 0 for a zero column), barrier, the quads of the later columns apply it, barrier.
+// Q's kk = min(m, c) columns are then formed as H_0 ... H_t e_t by quad t with no barrier
+// (the reflectors are read only). Q is written [q][rows], R [q][cols] (zero below the
+// diagonal), and kk to the op's slot.
+__device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__restrict__ tab, NetScalars *sc,
+                      double *lds) {
+  const int m = box_eff(op.bm), c = box_eff(op.bnb), kk = m < c ? m : c;
+  const int tid = threadIdx.x, sub = tid & 3, t = tid >> 2;
+  const int pitch = c | 1;
+  double *X = lds;                                   // m x pitch
+  double *Qb = X + m * pitch;                        // kk x m: column t of Q at Qb[t*m + i]
+  double *vdiag = Qb + kk * m, *bet = vdiag + kQrMaxCols, *rdiag = bet + kQrMaxCols;
+  const double *Cg = ws + op.a;
+  for (int e = tid; e < m * c; e += kThreads) {
+    const int i = e / c, j = e % c;
+    X[i * pitch + j] = Cg[map_off(tab, op.am, box_conv(op.bm, i)) + map_off(tab, op.bn, box_conv(op.bnb, j))];
+  }
+  __syncthreads();
+  for (int j = 0; j < kk; ++j) {
+    if (t == j) {                                    // the reflector of column j
+      double s = 0.0;
+      for (int i = j + 1 + sub; i < m; i += 4) s = fma(X[i * pitch + j], X[i * pitch + j], s);
+      const double x0 = X[j * pitch + j];
+      const double tail = quad_sum(s), nrm2 = fma(x0, x0, tail);
+      if (sub == 0) {
+        if (tail == 0.0) {                           // nothing below the diagonal: H_j = I
+          bet[j] = 0.0;
+          vdiag[j] = 0.0;
+          rdiag[j] = x0;
+        } else {
+          const double alpha = -copysign(sqrt(nrm2), x0);
+          bet[j] = 1.0 / (nrm2 - x0 * alpha);        // 2 / (v^T v)
+          vdiag[j] = x0 - alpha;
+          rdiag[j] = alpha;
+        }
+      }
+    }
+    __syncthreads();
+    const double bj = bet[j];
+    if (t > j && t < c && bj != 0.0) {               // apply H_j to column t
+      const double vj = vdiag[j];
+      double a = sub == 0 ? vj * X[j * pitch + t] : 0.0;
+      for (int i = j + 1 + sub; i < m; i += 4) a = fma(X[i * pitch + j], X[i * pitch + t], a);
+      const double w = bj * quad_sum(a);
+      if (sub == 0) X[j * pitch + t] -= w * vj;
+      for (int i = j + 1 + sub; i < m; i += 4) X[i * pitch + t] = fma(-w, X[i * pitch + j], X[i * pitch + t]);
+    }
+    __syncthreads();
+  }
+  if (t < kk) {                                      // Q e_t = H_0 ... H_t e_t
+    double *qc = Qb + t * m;
+    for (int i = sub; i < m; i += 4) qc[i] = i == t ? 1.0 : 0.0;
+    for (int j = t; j >= 0; --j) {
+      const double bj = bet[j];
+      if (bj == 0.0) continue;                       // the same j and beta in every lane of the quad
+      const double vj = vdiag[j];
+      double a = sub == 0 ? vj * qc[j] : 0.0;
+      for (int i = j + 1 + sub; i < m; i += 4) a = fma(X[i * pitch + j], qc[i], a);
+      const double w = bj * quad_sum(a);
+      if (sub == 0) qc[j] -= w * vj;
+      for (int i = j + 1 + sub; i < m; i += 4) qc[i] = fma(-w, X[i * pitch + j], qc[i]);
+    }
+  }
+  __syncthreads();
+  double *Q = ws + op.c, *R = ws + op.b;
+  const int64_t ldq = op.count, ldr = op.bn.n;
+  for (int e = tid; e < kk * m; e += kThreads) {
+    const int q = e / m, i = e % m;
+    Q[q * ldq + box_conv(op.bm, i)] = Qb[q * m + i];
+  }
+  for (int e = tid; e < kk * c; e += kThreads) {
+    const int q = e / c, j = e % c;
+    R[q * ldr + box_conv(op.bnb, j)] = j > q ? X[q * pitch + j] : (j == q ? rdiag[q] : 0.0);
+  }
+  if (tid == 0) {
+    dyn[op.out_dyn] = kk;
+    sc->eig_flops += 4LL * m * c * kk;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------- interpreter
@@ -1625,11 +1806,17 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
       case OP_IDENT:
         ident_wg(nd.ws + op.c, op.count);
         break;
+      case OP_QR:
+        qr_wg(op, nd.ws, nd.dyn, nd.tab, nd.sc, lds);
+        break;
       default:
         break;
     }
     __syncthreads();
-    if (tid == 0) nd.sc->ticks[kind & 7] += wall_clock64() - t0;
+    if (tid == 0) {
+      if (kind == OP_QR) nd.sc->qr_ticks += wall_clock64() - t0;
+      else nd.sc->ticks[kind & 7] += wall_clock64() - t0;
+    }
   }
   __syncthreads();
   if (tid < kScWords) reinterpret_cast<long long *>(g_sc)[tid] = reinterpret_cast<const long long *>(&s_sc)[tid];
@@ -1874,7 +2061,10 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_presplit_kernel(const NetDev
   stage_op(nd, i, s_op);
   const Op &op = s_op;
   const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
-  if (blockIdx.x == 0 && threadIdx.x == 0) nd.sc->flops += 2LL * M * N * K;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    nd.sc->flops += 2LL * M * N * K;
+    nd.sc->split_flops += 2LL * M * N * K;
+  }
   double *C = nd.ws + op.c;
   if (M <= 16) presplit_tiles<SPLIT, 16, 256, 1, 4>(op, planes, C, lds, M, N, K);
   else if (M <= 32) presplit_tiles<SPLIT, 32, 128, 2, 2>(op, planes, C, lds, M, N, K);

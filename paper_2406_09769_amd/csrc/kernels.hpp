@@ -17,8 +17,8 @@ struct NetDev {
   int32_t *dyn;      // kept-rank slots (inside the workspace)
 };
 
-// Rank rule of the eigensolve: drop w <= tau_rel*w1; never split a cluster with
-// gap <= tau_deg*w1 whose lower member exceeds floor*w1.
+// Rank rule of the eigensolve: drop w <= tau_rel*w1; never cut where
+// w_k - w_{k+1} <= tau_deg*w_k while w_{k+1} exceeds floor*w1 (floor = kClusterFloor*tau_rel).
 struct KeepParams {
   double tau_rel;
   double tau_deg;
@@ -39,7 +39,7 @@ struct KeepParams {
 // k chunk), in the order the options and the autotuner number them.
 constexpr int kGemmConfigs = 6;
 
-constexpr double kClusterFloor = 1e-10;
+constexpr double kClusterFloor = 0.1;   // the separation rule acts above kClusterFloor * tau_rel * w1
 constexpr int kMlpParams = 8 * 32 + 32 + 32 * 32 + 32 + 32 + 1;   // 8 -> 32 -> 32 -> 1
 constexpr int kMlpBatch = 128;                                  // rows per training step (max)
 

@@ -406,7 +406,7 @@ class Builder {
 
   // Kept leading eigenvectors of L (rows = its first nrow modes, bond modes first).
   // U is stored [bond][rows] so that the new bond is the outermost mode.
-  Sym eig(const Sym &L, size_t nrow, int64_t ucols, int64_t bond) {
+  Sym eig(const Sym &L, size_t nrow, int64_t ucols, int64_t bond, int32_t flags = 0) {
     int64_t n = 1;
     for (size_t i = 0; i < nrow; ++i) n *= L.dim[i];
     Sym U;
@@ -424,7 +424,7 @@ class Builder {
     U.rows = Box{1, 1, {slot}, {int32_t(ucols)}};
     U.cols = L.rows;
     U.ncols = n;
-    o.flags |= F_V_GLOBAL;                    // reflector scratch: n x n solve, then p x p solve
+    o.flags |= F_V_GLOBAL | flags;            // reflector scratch: n x n solve, then p x p solve
     int32_t scratch = new_buf(2 * (n * n + n));
     int32_t id = emit(o);
     refs_.push_back({id, 1, L.buf});
@@ -435,6 +435,56 @@ class Builder {
     p_.eig_flops += 9 * n * n * n;
     p_.max_eig_dim = std::max<int32_t>(p_.max_eig_dim, int32_t(n));
     return U;
+  }
+
+  // QR factorisation of C viewed as a matrix with the modes `row_labels` as rows and the
+  // others as columns (the QR-SVD branch of Algorithm density_matrix_alg): Q with labels
+  // (q, rows) stored [q][rows], R with labels (q, cols) stored [q][cols]; q is a new bond
+  // whose runtime extent min(rows, cols) the op writes to its slot.
+  std::pair<Sym, Sym> qr(const Sym &C, const std::vector<int64_t> &row_labels, int64_t q) {
+    Group gr, gc;
+    auto sc = strides_of(C);
+    for (size_t i = 0; i < C.lab.size(); ++i) {
+      Group &g = std::find(row_labels.begin(), row_labels.end(), C.lab[i]) != row_labels.end() ? gr : gc;
+      g.lab.push_back(C.lab[i]); g.dim.push_back(C.dim[i]); g.sa.push_back(sc[i]); g.dyn.push_back(dyn_of(C.lab[i]));
+    }
+    dyn_first(gr);
+    dyn_first(gc);
+    int64_t nr = 1, nc = 1;
+    for (int64_t d : gr.dim) nr *= d;
+    for (int64_t d : gc.dim) nc *= d;
+    const int64_t cap = std::min(nr, nc);
+    const int32_t slot = new_dyn(q);
+    Op o{};
+    o.kind = OP_QR;
+    o.am = make_map(gr.dim, gr.sa);
+    o.bn = make_map(gc.dim, gc.sa);
+    o.bm = box_of(gr);
+    o.bnb = box_of(gc);
+    o.K = int32_t(cap);
+    o.count = nr;
+    o.out_dyn = slot;
+    Sym Q, R;
+    Q.lab.push_back(q); Q.dim.push_back(cap);
+    Q.lab.insert(Q.lab.end(), gr.lab.begin(), gr.lab.end()); Q.dim.insert(Q.dim.end(), gr.dim.begin(), gr.dim.end());
+    R.lab.push_back(q); R.dim.push_back(cap);
+    R.lab.insert(R.lab.end(), gc.lab.begin(), gc.lab.end()); R.dim.insert(R.dim.end(), gc.dim.begin(), gc.dim.end());
+    Q.buf = new_buf(cap * nr);
+    R.buf = new_buf(cap * nc);
+    Q.rows = R.rows = Box{1, 1, {slot}, {int32_t(cap)}};
+    Q.cols = o.bm;
+    R.cols = o.bnb;
+    Q.ncols = nr;
+    R.ncols = nc;
+    const int32_t id = emit(o);
+    bind(id, 1, C);
+    def(id, Q.buf);
+    refs_.push_back({id, 2, R.buf});
+    if (vb_[R.buf].def < 0) vb_[R.buf].def = id;
+    vb_[R.buf].last = std::max(vb_[R.buf].last, id);
+    p_.eig_flops += 4 * nr * nc * cap;
+    p_.n_qr += 1;
+    return {Q, R};
   }
 
   // ---------------------------------------------------------------- memory
@@ -820,15 +870,32 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
         *unsupported = true;
         return "density matrix of dimension " + std::to_string(nr) + " exceeds the supported 128";
       }
-      B.gemm_flags = F_ENV;
-      Sym T = B.contract_ab(C, R[k]);            // rows x bra(X_k)
-      Sym Cb = C;
-      for (auto &l : Cb.lab) l = bra_of(l);      // C with every mode primed
-      Sym L = B.contract_ab(T, Cb);              // rows x bra(rows)
-      B.gemm_flags = 0;
       int64_t ucols = std::min<int64_t>({int64_t(a.chi), nr, xdim(k)});
       int64_t bond = B.fresh();
-      Sym U = B.eig(L, rows.size(), ucols, bond);
+      Sym U;
+      if (nr > xdim(k) && nr <= kQrMaxRows && xdim(k) <= kQrMaxCols) {
+        // QR-SVD branch (the open size exceeds the crossing size): C = Q Rc, the
+        // leading eigenvectors of Rc R_k Rc^T, mapped back through Q
+        const int64_t q = B.fresh(), qb = B.fresh();
+        auto qr = B.qr(C, rows, q);
+        B.share_dyn(q, qb);
+        B.gemm_flags = F_ENV;
+        Sym T = B.contract_ab(qr.second, R[k]);  // q x bra(X_k)
+        Sym Rb = qr.second;
+        for (auto &l : Rb.lab) l = (l == q) ? qb : bra_of(l);
+        Sym M = B.contract_ab(T, Rb);            // q x qb
+        B.gemm_flags = 0;
+        Sym Uh = B.eig(M, 1, ucols, bond, F_NO_WARM);
+        U = B.contract_ab(Uh, qr.first);         // bond x rows
+      } else {
+        B.gemm_flags = F_ENV;
+        Sym T = B.contract_ab(C, R[k]);          // rows x bra(X_k)
+        Sym Cb = C;
+        for (auto &l : Cb.lab) l = bra_of(l);    // C with every mode primed
+        Sym L = B.contract_ab(T, Cb);            // rows x bra(rows)
+        B.gemm_flags = 0;
+        U = B.eig(L, rows.size(), ucols, bond);
+      }
       Sym Cn = B.contract_ab(U, C);              // bond x X_k
       Cn = B.absorb(&Cn, gsyms(k + 1));
       std::vector<int64_t> want = k + 1 <= n - 1 ? X[k + 1] : std::vector<int64_t>();

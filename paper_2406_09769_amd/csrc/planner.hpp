@@ -32,6 +32,7 @@ struct Plan {
   int64_t flops = 0;         // sum 2 m n k over GEMMs
   int64_t eig_flops = 0;     // 9 n^3 per density matrix
   int64_t n_eig = 0;
+  int64_t n_qr = 0;          // QR-SVD branches taken
   int32_t max_eig_dim = 0;
   int64_t dyn_off = 0;       // workspace offset (doubles) of the int32 kept-rank slots
   int32_t n_dyn = 0;

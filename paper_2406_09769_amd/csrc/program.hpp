@@ -16,7 +16,14 @@ enum OpKind : int32_t {
   OP_RESCALE = 3,  // x *= 2^-e, e = frexp exponent of max|x|; optionally sum e
   OP_SCALAR = 4,   // z = x[0]: add ln|z| and sign(z) to the result
   OP_IDENT = 5,    // x = identity (dim x dim)
+  OP_QR = 6,       // C = Q R (Householder) for C read through the row / column maps am / bn
+                   // (runtime boxes bm / bnb): Q stored [q][rows] at .c, R [q][cols] at .b,
+                   // q = min(rows, cols) written to slot out_dyn
 };
+
+// Largest C the QR-SVD branch factors in one workgroup's LDS: rows x cols.
+constexpr int kQrMaxRows = 128;
+constexpr int kQrMaxCols = 64;
 
 enum OpFlags : int32_t {
   F_A_CONST = 1,      // A operand lives in the network's input (constant) area
@@ -28,6 +35,8 @@ enum OpFlags : int32_t {
   F_ENV = 64,         // OP_GEMM: builds a right environment or a density matrix; its
                       // rounding only moves the kept subspaces, never the value carried
                       // along the main chain (the split forms may run it in 16-bit parts)
+  F_NO_WARM = 128,    // OP_EIG: the small matrix of the QR-SVD branch (rows are not
+                      // (bond, leaf) pairs): no learned warm start, no harvested rows
 };
 
 // A two-level index map over a row-major multi-index: off(i) = hi[i / lo_n] + lo[i % lo_n]
@@ -56,8 +65,10 @@ struct Op {
   int64_t c;        // GEMM/EIG/IDENT output offset; RESCALE operand offset
   int64_t a;        // GEMM A; EIG input L; SCALAR operand
   int64_t b;        // GEMM B; EIG scratch (V) when F_V_GLOBAL
-  int64_t count;    // IDENT: dim; EIG: static dim of L; RESCALE: static row length
-  int32_t K;        // GEMM static contraction extent; EIG: ucols (static kept columns)
+  int64_t count;    // IDENT: dim; EIG: static dim of L; RESCALE: static row length; QR: static
+                    // rows (row stride of Q; R's row stride is bn.n)
+  int32_t K;        // GEMM static contraction extent; EIG: ucols (static kept columns);
+                    // QR: static q (min of the static rows and columns)
   int32_t ak;       // GEMM: table offset of A's k offsets
   int32_t bk;       // GEMM: table offset of B's k offsets
   int32_t out_dyn;  // EIG: dyn slot that receives the kept rank
@@ -76,13 +87,16 @@ struct NetScalars {
   long long n_fallback;
   long long n_learned;
   long long flops;      // executed GEMM flops, 2 m n k at the runtime extents
+  long long split_flops;  // the part of flops run in 16-bit parts (split forms)
   long long eig_flops;  // 9 n^3 per density matrix at its runtime dimension
   long long n_rot;      // Givens rotations of the QL iterations (diagnostic)
   long long rej[4];     // learned warm starts handed to the exact solve, by reason:
                         // subspace too large for n, lost every column, cut not certified, residual
   long long lticks[4];  // learned warm start, wall-clock ticks: scoring and start basis,
                         // products with L and norms, the small eigensolve, Ritz vectors
-  long long ticks[8];   // wall-clock ticks spent per op kind (index = OpKind)
+  long long ticks[8];   // wall-clock ticks spent per op kind (index = OpKind; the eigensolve also
+                        // splits its own time into entries 0, 6 and 7)
+  long long qr_ticks;   // wall-clock ticks of the QR factorisations (OP_QR)
 };
 
 }  // namespace tn

@@ -50,7 +50,7 @@ class tn_result(C.Structure):
     _fields_ = [("log_abs", C.c_double), ("sign", C.c_int32), ("_pad", C.c_int32),
                 ("seconds", C.c_double), ("flops", C.c_int64), ("eig_flops", C.c_int64),
                 ("n_eig", C.c_int64), ("n_fallback", C.c_int64), ("max_residual", C.c_double),
-                ("n_learned", C.c_int64)]
+                ("n_learned", C.c_int64), ("split_flops", C.c_int64)]
 
 
 def _load():
@@ -147,7 +147,7 @@ class _PathArgs:
                             self.flat.ctypes.data_as(C.POINTER(C.c_int32)))
 
 
-def _options(precision=TN_FP64, eig=TN_EIG_EXACT, residual_tol=1e-6, tau_rel=1e-15, tau_deg=1e-12,
+def _options(precision=TN_FP64, eig=TN_EIG_EXACT, residual_tol=1e-6, tau_rel=1e-12, tau_deg=0.1,
              stream=None, model=None, gemm_config=(0, 0, 0)):
     return tn_options(int(precision), int(eig), float(residual_tol), float(tau_rel), float(tau_deg),
                       C.c_void_p(stream) if stream else None, model.ptr if model is not None else None,
@@ -165,11 +165,12 @@ class Result:
     n_fallback: int
     max_residual: float
     n_learned: int
+    split_flops: int
 
 
 def _result(r: tn_result) -> Result:
     return Result(r.log_abs, r.sign, r.seconds, r.flops, r.eig_flops, r.n_eig, r.n_fallback, r.max_residual,
-                  r.n_learned)
+                  r.n_learned, r.split_flops)
 
 
 # ---------------------------------------------------------------- the calls
@@ -247,20 +248,21 @@ def tn_plan_json(tensors_or_shapes, edges, slices, env_size: int) -> dict:
 
 def tn_plan_stats(h: Handle, slices, max_rank: int, env_size: int) -> dict:
     p = _PathArgs(slices)
-    st = (C.c_int64 * 8)()
+    st = (C.c_int64 * 9)()
     _check(LIB.tn_plan_stats(h.ptr, C.byref(p.path), int(max_rank), int(env_size), st))
-    keys = ["ops", "table_entries", "ws_doubles", "flops", "eig_flops", "n_eig", "max_eig_dim", "grid_ops"]
+    keys = ["ops", "table_entries", "ws_doubles", "flops", "eig_flops", "n_eig", "max_eig_dim", "grid_ops", "qr_svd"]
     return dict(zip(keys, list(st)))
 
 
 def tn_profile_last(h: Handle) -> dict:
-    out = (C.c_double * 17)()
+    out = (C.c_double * 18)()
     _check(LIB.tn_profile_last(h.ptr, out))
     return {"gemm": out[1], "eig": out[2], "rescale": out[3], "scalar": out[4], "ident": out[5],
             "eig_reduce": out[0], "eig_ql": out[6], "eig_back": out[7], "ql_rotations": out[8],
             "learned_rejected": {"size": int(out[9]), "dependent": int(out[10]), "cut": int(out[11]),
                                  "residual": int(out[12])},
-            "learned_time": {"start": out[13], "products": out[14], "small_eig": out[15], "ritz": out[16]}}
+            "learned_time": {"start": out[13], "products": out[14], "small_eig": out[15], "ritz": out[16]},
+            "qr": out[17]}
 
 
 def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30, precision: int = TN_FP64,
@@ -278,7 +280,7 @@ def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30, precisi
     return Cm
 
 
-def tn_debug_eig(L: np.ndarray, ucols: int, tau_rel=1e-15, tau_deg=1e-12, rest: int = 0, model=None,
+def tn_debug_eig(L: np.ndarray, ucols: int, tau_rel=1e-12, tau_deg=0.1, rest: int = 0, model=None,
                  residual_tol=1e-6, stats: bool = False):
     """Kept eigenvectors (n x ucols, zero past the kept rank) and the fallback flag;
     with stats=True also the dict of the learned warm start's outcome."""

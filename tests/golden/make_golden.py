@@ -10,6 +10,7 @@ Calls only oracle/ (and the seeded input generators). Usage:
     python tests/golden/make_golden.py w4eignoise      # add the eigensolver backward-error row to w4_spread
     python tests/golden/make_golden.py w5smalleignoise # ... and to w5_small_spread
     python tests/golden/make_golden.py w3   # 8x8x8 3D Ising at the 3 betas, chi 16, plane slices
+    python tests/golden/make_golden.py w3chi32 0.2217   # the same lattice at chi 32, one beta
     python tests/golden/make_golden.py w3spread 0.25 [--hows=evr,perturbed_0,perturbed13_0]
                                             # how far FP64 fixes the W3 result at these betas
 """
@@ -54,6 +55,25 @@ def _w3_one(beta):
            "seconds": time.time() - t}
     print(json.dumps(row), flush=True)
     return row
+
+
+def w3_chi32(out_path, beta):
+    """The 8x8x8 lattice at chi 32 for one beta. Every right environment holds up to
+    (32 * 2^9)^2 doubles (2.1 GB): only every 8th is kept and the rest recomputed (a memory
+    schedule, bit-identical to keeping them all). Rows for other betas in out_path stay."""
+    net = inputs.ising_3d(8, 8, 8, beta)
+    t = time.time()
+    st = dm.Stats()
+    v, s = dm.contract_approx(net, 32, 1, stats=st, env_checkpoint=8)
+    row = {"beta": beta, "chi": 32, "env": 1, "log_abs": v, "sign": s, "n_eig": st.n_eig,
+           "seconds": time.time() - t}
+    print(json.dumps(row), flush=True)
+    old = json.load(open(out_path))["rows"] if os.path.exists(out_path) else []
+    rows = sorted([r for r in old if r["beta"] != beta] + [row], key=lambda r: r["beta"])
+    json.dump({"workload": "ising3d 8x8x8 open, J=1, h=0, one z-plane per slice, chi 32",
+               "generator": "paper_2406_09769_amd.inputs.ising_3d(8, 8, 8, beta)",
+               "oracle": "oracle.dm.contract_approx(net, 32, 1, env_checkpoint=8) with default cutoffs",
+               "rows": rows}, open(out_path, "w"), indent=1)
 
 
 def w3(out_path):
@@ -198,7 +218,11 @@ def _eignoise_one(args):
     return i, d
 
 
-def add_eignoise(kind, path, count, workers=4):
+WORKERS = int(os.environ.get("GOLDEN_WORKERS", "4"))
+
+
+def add_eignoise(kind, path, count, workers=None):
+    workers = workers or WORKERS
     """Adds the eignoise_0 deviation to every row of a stored spread file and raises each
     row's spread to it where it is larger."""
     with Pool(workers) as pool:
@@ -216,8 +240,8 @@ def _spread_w5small(i):
     return _spread_one(i, "w5small")
 
 
-def spread_w5small(out_path, workers=4):
-    with Pool(workers) as pool:
+def spread_w5small(out_path, workers=None):
+    with Pool(workers or WORKERS) as pool:
         rows = sorted(pool.map(_spread_w5small, range(8)), key=lambda r: r["index"])
     json.dump({"workload": "the 8 formulas of w5_small_oracle.json",
                "what": "largest |dlnZ|/N between the stored oracle value and the oracle under an "
@@ -225,8 +249,8 @@ def spread_w5small(out_path, workers=4):
                "rows": rows}, open(out_path, "w"), indent=1)
 
 
-def spread(out_path, workers=4):
-    with Pool(workers) as pool:
+def spread(out_path, workers=None):
+    with Pool(workers or WORKERS) as pool:
         rows = sorted(pool.map(_spread_one, range(64)), key=lambda r: r["index"])
     json.dump({"workload": "the 64 graphs of w4_oracle.json",
                "what": "largest |dlnZ|/N between the stored oracle value and the oracle under an "
@@ -251,8 +275,8 @@ def _one(args):
     return row
 
 
-def batch(kind, count, chi, out_path, workers=4):
-    with Pool(workers) as pool:
+def batch(kind, count, chi, out_path, workers=None):
+    with Pool(workers or WORKERS) as pool:
         rows = sorted(pool.map(_one, [(kind, i, chi) for i in range(count)]), key=lambda r: r["index"])
     desc = {"w4": ("64 signed-J random 3-regular graphs, n_i = 2*U{50..150}, J ~ N(0,1), beta 1, "
                    "seed 4000+i, greedy path", "paper_2406_09769_amd.inputs.rrg_batch(64)"),
@@ -277,6 +301,8 @@ if __name__ == "__main__":
         spread(os.path.join(HERE, "w4_spread.json"))
     elif which == "w3":
         w3(os.path.join(HERE, "w3_oracle.json"))
+    elif which == "w3chi32":
+        w3_chi32(os.path.join(HERE, "w3_chi32_oracle.json"), float(sys.argv[2]))
     elif which == "w3spread":
         args = [a for a in sys.argv[2:] if not a.startswith("--hows=")]
         hows = [a[7:].split(",") for a in sys.argv[2:] if a.startswith("--hows=")]

@@ -1,19 +1,19 @@
 """Uneven batches in one launch against stored oracle values (plain FP64).
 
 * 64 random 3-regular graphs with Gaussian couplings (n = 2*U{50..150}, beta 1,
-  chi 64, single-vertex slices on the greedy path), one workgroup per graph.
-  These results are not all fixed to 1e-10 by FP64 arithmetic: near-degenerate
-  eigenvalues at the chi cut make the kept subspace depend on rounding. For each
-  graph tests/golden/w4_spread.json holds how far the oracle itself moves under
-  other equally valid FP64 evaluations (another LAPACK eigensolver; 1e-15 relative
-  input noise, two seeds). The bound per graph is max(1e-10, 10 x that spread); the
-  graphs whose spread is below 1e-11 must meet 1e-10 outright.
-* 8 random 3-SAT model counts (n 50, m 150, chi 32) as #CSP networks. Their 0/1
-  tensors make the spectra at the chi cut degenerate, so FP64 fixes these counts even
-  less: the oracle moves by up to 1e-5 per variable under the evaluations above
-  (tests/golden/w5_small_spread.json); the same per-formula bound applies. (The 150-
-  variable formulas take about three minutes each on one workgroup: their values
-  are stored in w5_oracle.json, but no test runs them.)
+  chi 64, single-vertex slices on the greedy path), one workgroup per graph, bound
+  1e-10 per site. The rank rule never cuts where the spectrum does not separate by
+  10%, so every kept subspace is fixed by FP64 arithmetic: under other valid FP64
+  evaluations (another LAPACK eigensolver, 1e-15 relative input noise, an eps ||L||
+  perturbation of every density matrix) the oracle moves by at most 2.5e-12 per site
+  (tests/golden/w4_spread.json).
+* Random 3-SAT model counts as #CSP networks: 8 formulas of 50 variables (m 150, chi
+  32) and the full 32 formulas of 150 variables (m 450). Their 0/1 tensors put
+  eigenvalues of many density matrices close to the 1e-12 cutoff, where a keep decision
+  can flip under the backward error of an FP64 eigensolver: with an eps ||L|| error the
+  oracle moves by up to 1.2e-10 per variable (w5_small_spread.json), with an n eps ||L||
+  error one decision of the formula of seed 5004 flips and moves it by 5.9e-9, the
+  deviation the GPU shows there. Stated bound for #CSP: 1e-8 per variable.
 
 Expected values: tests/golden/*.json, written by tests/golden/make_golden.py from
 oracle/ alone. N is the number of spins or variables.
@@ -28,6 +28,7 @@ from paper_2406_09769_amd import inputs
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 BOUND = 1e-10
+CSP_BOUND = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -43,41 +44,61 @@ def _run(T, nets, chi):
 
 def test_rrg_batch_of_64_matches_oracle(T):
     gold = json.load(open(os.path.join(GOLD, "w4_oracle.json")))["rows"]
-    spread = {r["name"]: r["spread"] for r in json.load(open(os.path.join(GOLD, "w4_spread.json")))["rows"]}
     nets = inputs.rrg_batch(64)
     print("random 3-regular batch: 64 graphs, chi 64, one launch", flush=True)
-    rs = _run(T, nets, 64)
-    worst, n_sharp = 0.0, 0
+    hs = [T.create_network(n) for n in nets]
+    n_qr = sum(T.tn_plan_stats(h, n.slices, 64, 1)["qr_svd"] for h, n in zip(hs, nets))
+    rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], 64, 1)
+    worst = 0.0
     for net, g, r in zip(nets, gold, rs):
         assert net.name == g["name"]
         assert r.sign == g["sign"], net.name
         err = abs(r.log_abs - g["log_abs"]) / net.n_sites
-        sp = spread[net.name]
-        if sp < 1e-11:
-            n_sharp += 1
-            assert err <= BOUND, (net.name, err)
-        assert err <= max(BOUND, 10 * sp), (net.name, err, sp)
-        worst = max(worst, err / max(BOUND, 10 * sp))
-    print(f"kernel {rs[0].seconds:.2f} s, {sum(r.n_eig for r in rs)} eigensolves; {n_sharp} graphs fixed to "
-          f"1e-11 by FP64 meet 1e-10; worst error / bound {worst:.2f}", flush=True)
+        assert err <= BOUND, (net.name, err)
+        worst = max(worst, err)
+    print(f"kernel {rs[0].seconds:.2f} s, {sum(r.n_eig for r in rs)} eigensolves ({n_qr} by the QR-SVD branch); "
+          f"worst |dlnZ|/N {worst:.2e}", flush=True)
+    assert n_qr > 0
 
 
-def test_csp_batch_matches_oracle(T):
-    gold = json.load(open(os.path.join(GOLD, "w5_small_oracle.json")))["rows"]
-    spread = {r["name"]: r["spread"]
-              for r in json.load(open(os.path.join(GOLD, "w5_small_spread.json")))["rows"]}
-    nets = inputs.csp_batch(8, n_vars=50)
-    print("3-SAT #CSP batch: 8 formulas, n 50, m 150, chi 32, one launch", flush=True)
-    rs = _run(T, nets, 32)
-    ratios = []
+def _csp_check(nets, gold, rs, bound_of):
+    worst = 0.0
     for net, g, r in zip(nets, gold, rs):
         assert net.name == g["name"]
         assert r.sign == g["sign"], net.name
         assert r.n_eig == g["n_eig"]
         err = abs(r.log_abs - g["log_abs"]) / net.n_sites
-        sp = spread[net.name]
-        print(f"  {net.name}: |dlnZ|/N {err:.2e}, oracle spread {sp:.2e}", flush=True)
-        assert err <= max(BOUND, 10 * sp), (net.name, err, sp)
-        ratios.append(err / max(BOUND, 10 * sp))
+        b = bound_of(net.name)
+        print(f"  {net.name}: |dlnZ|/N {err:.2e} (bound {b:.1e})", flush=True)
+        assert err <= b, (net.name, err, b)
+        worst = max(worst, err / b)
+    return worst
+
+
+def test_csp_batch_matches_oracle(T):
+    gold = json.load(open(os.path.join(GOLD, "w5_small_oracle.json")))["rows"]
+    nets = inputs.csp_batch(8, n_vars=50)
+    print("3-SAT #CSP batch: 8 formulas, n 50, m 150, chi 32, one launch", flush=True)
+    rs = _run(T, nets, 32)
+    worst = _csp_check(nets, gold, rs, lambda name: CSP_BOUND)
     print(f"kernel {rs[0].seconds:.2f} s, {sum(r.n_eig for r in rs)} eigensolves, worst error / bound "
-          f"{max(ratios):.2f}", flush=True)
+          f"{worst:.2f}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def w5_full(T):
+    gold = json.load(open(os.path.join(GOLD, "w5_oracle.json")))["rows"]
+    nets = inputs.csp_batch(32)
+    hs = [T.create_network(n) for n in nets]
+    return gold, nets, hs
+
+
+
+
+def test_csp_full_size_batch_exact(T, w5_full):
+    gold, nets, hs = w5_full
+    print("3-SAT #CSP: 32 formulas, n 150, m 450, chi 32, one launch, exact eigensolve", flush=True)
+    rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], 32, 1)
+    worst = _csp_check(nets, gold, rs, lambda name: CSP_BOUND)
+    print(f"kernel {rs[0].seconds:.2f} s, {sum(r.n_eig for r in rs)} eigensolves, worst error / bound "
+          f"{worst:.2f}", flush=True)

@@ -59,23 +59,32 @@ def test_gradient_matches_numpy_backprop(T):
 def test_harvest_matches_oracle_density_matrices(T):
     net = inputs.ising_2d(6, 6, 0.44)
     ds = T.Dataset(100_000)
-    T.tn_harvest(T.create_network(net), net.slices, 4, 1, ds)
+    h = T.create_network(net)
+    T.tn_harvest(h, net.slices, 4, 1, ds)
+    n_qr = T.tn_plan_stats(h, net.slices, 4, 1)["qr_svd"]
     X, y = ds.read()
     st = dm.Stats()
     dm.contract_approx(net, 4, 1, stats=st, harvest=True)
-    # rows are grouped per density matrix in sweep order; compare per matrix as sorted sets
-    off = 0
-    for i, (L, k) in enumerate(st.harvest):
+    # rows are grouped per density matrix in sweep order, each matrix's rows in (bond, leaf)
+    # order on both sides: all eight features and the leverage agree row by row (the
+    # device stores them in FP32). Where the device takes the QR-SVD branch (decided from
+    # static capacities) it forms no density matrix and harvests nothing: every oracle
+    # matrix either matches the next device block or is one of exactly n_qr skipped.
+    off, skipped, matched = 0, 0, 0
+    for i, (L, k, nr, d) in enumerate(st.harvest):
         n = L.shape[0]
         U, _, kk, _ = dm.keep(L, 4)
         fo = mlp.features(L, 2, i % 4 != 0 and n > 4)
         lev = mlp.leverage(U)
         xs, ys = X[off:off + n], y[off:off + n]
+        if len(ys) < n or not (np.allclose(ys, lev, rtol=0, atol=1e-5)
+                               and np.allclose(xs, fo, rtol=1e-5, atol=1e-6)):
+            skipped += 1
+            continue
+        matched += 1
         off += n
-        assert np.allclose(np.sort(ys), np.sort(lev), atol=1e-5)
-        assert np.allclose(np.sort(xs[:, 0]), np.sort(fo[:, 0]), atol=1e-5)
-        assert np.allclose(np.sort(xs[:, 4]), np.sort(fo[:, 4]), atol=1e-5)
-    assert off == len(y)
+    print(f"harvested matrices matched {matched}, taken by the QR-SVD branch {skipped} (device: {n_qr})", flush=True)
+    assert off == len(y) and skipped == n_qr and matched > 0
 
 
 def test_training_lowers_the_loss(trained):
@@ -96,8 +105,9 @@ def test_learned_contraction_within_bound(T, trained, L, beta, chi, env):
     print(f"{net.name} chi={chi} env={env}: learned {r.n_learned}/{r.n_eig} warm starts, handed to the "
           f"exact solve {rej}, max residual {r.max_residual:.2e}, |dlnZ|/N {err:.2e}", flush=True)
     assert r.sign == s and err <= BOUND
-    eligible = r.n_eig - rej["size"]
-    assert r.n_learned + sum(rej.values()) == r.n_eig
+    n_qr = T.tn_plan_stats(h, net.slices, chi, env)["qr_svd"]     # small QR-SVD solves: no warm start
+    eligible = r.n_eig - n_qr - rej["size"]
+    assert r.n_learned + sum(rej.values()) + n_qr == r.n_eig
     assert eligible > 0 and r.n_learned >= 0.5 * eligible
 
 
@@ -110,7 +120,7 @@ def test_learned_solve_matches_oracle_rule(T):
     st = dm.Stats()
     dm.contract_approx(inputs.ising_2d(16, 16, 0.44), 16, 1, stats=st, harvest=True)
     agree = total = acc = rank_diff = 0
-    for L, _ in st.harvest:
+    for L, *_ in st.harvest:
         n = L.shape[0]
         if n < 16:
             continue
@@ -143,7 +153,7 @@ def test_learned_solve_matches_oracle_rule(T):
     print(f"learned solves: device accepted {acc}/{total}, decisions agree with the rule on {agree}/{total}, "
           f"kept ranks differ below TAIL_REL on {rank_diff}", flush=True)
     assert acc > 0.5 * total
-    assert agree >= 0.95 * total
+    assert agree == total
 
 
 def test_learned_batch_full_size_within_bound(T, trained):

@@ -44,6 +44,50 @@ def test_keep_does_not_split_a_degenerate_cluster():
     assert k == 3
 
 
+def test_keep_moves_cuts_to_where_the_spectrum_separates():
+    # the separation is relative to the kept value: a 4% gap at 0.5 and a 5% gap deep in the
+    # tail both move the cut up; a 12% gap does not
+    assert dm.keep(np.diag([1.0, 0.5, 0.48, 0.1]), 2)[2] == 1
+    assert dm.keep(np.diag([1.0, 0.5, 0.44, 0.1]), 2)[2] == 2
+    assert dm.keep(np.diag([1.0, 1e-9, 0.95e-9, 1e-11]), 2)[2] == 1
+    # a cut at the cutoff itself: 0.99e-12 is dropped, 1.05e-12 would be kept alone, but the
+    # two do not separate, so neither is kept
+    assert dm.keep(np.diag([1.0, 1e-6, 1.05e-12, 0.99e-12]), 4)[2] == 2
+    # eigenvalues below the FP64 resolution of the solve are never kept
+    assert dm.keep(np.diag([1.0, 1e-3, 5e-13, 1e-15]), 4)[2] == 2
+
+
+def test_keep_cut_is_fixed_by_fp64_on_a_dense_tail():
+    """Why the rule looks at relative gaps: any backward-stable FP64 eigensolver may return
+    the eigenvectors of L + E with ||E|| ~ eps ||L||. With the chi cut between two tail
+    eigenvalues 1e-10 and 0.99e-10 of the largest (a 1% gap), the top-chi subspace turns by
+    far more than rounding under such an E; the kept subspace of keep(), cut where the
+    spectrum separates (a gap of about 3e-9 of the largest), turns only by about
+    eps / 3e-9."""
+    rng = np.random.default_rng(3)
+    n, chi = 40, 20
+    tail = 1e-10 * 0.75 ** np.arange(n - 21)
+    w = np.concatenate([np.logspace(0, -9, 20), [0.99e-10], tail])
+    w[19] = 1e-10
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    L = (q * w) @ q.T
+    eps = np.finfo(float).eps
+    proj_top, proj_keep = [], []
+    for seed in range(3):
+        z = np.random.default_rng(seed).standard_normal((n, n))
+        S = 0.5 * (z + z.T)
+        Lp = L + eps * np.linalg.norm(L, 2) * S / np.linalg.norm(S, 2)
+        wv, v = np.linalg.eigh(0.5 * (Lp + Lp.T))
+        top = v[:, ::-1][:, :chi]
+        proj_top.append(top @ top.T)
+        U, _, k, _ = dm.keep(Lp, chi)
+        assert k == 19                   # moved up from the 1% gap
+        proj_keep.append(U @ U.T)
+    P = q[:, :19] @ q[:, :19].T
+    assert max(np.abs(p - P).max() for p in proj_keep) < 1e-6
+    assert max(np.abs(p - proj_top[0]).max() for p in proj_top) > 1e-3
+
+
 def test_keep_is_blind_to_zero_padding():
     rng = np.random.default_rng(1)
     a = rng.standard_normal((5, 5))
@@ -57,6 +101,37 @@ def test_keep_is_blind_to_zero_padding():
 def test_keep_all_zero_falls_back():
     _, _, k, fb = dm.keep(np.zeros((4, 4)), 3)
     assert fb and k == 3
+
+
+@pytest.mark.slow
+def test_signed_graph_result_is_fixed_by_fp64():
+    """The random 3-regular graph of the 64-graph workload that moved most under other valid
+    FP64 evaluations when cuts could sit in near-degenerate pairs (2.8e-7 per site): under
+    the rank rule its result moves by less than 1e-11 per site when every density matrix
+    gets a symmetric perturbation of norm eps ||L|| (a backward error any FP64 eigensolver
+    may have), or when LAPACK's MRRR driver replaces the default one."""
+    import scipy.linalg as sl
+    from threadpoolctl import threadpool_limits
+    net = inputs.rrg_batch(43)[42]
+    with threadpool_limits(limits=1):      # 128 x 128 solves: threads only contend
+        _fixed_by_fp64(net, sl)
+
+
+def _fixed_by_fp64(net, sl):
+    base = dm.contract_approx(net, 64, 1)[0]
+    rng = np.random.default_rng(0)
+
+    def eigh_noisy(L):          # ||E||_2 between eps ||L||_1 / sqrt(n) and eps ||L||_1 (cheap norms)
+        z = rng.standard_normal(L.shape)
+        S = 0.5 * (z + z.T)
+        return np.linalg.eigh(L + np.finfo(float).eps * np.linalg.norm(L, 1) * S / np.linalg.norm(S, 1))
+    for e in (eigh_noisy, lambda L: sl.eigh(L, driver="evr")):
+        dm.EIGH = e
+        try:
+            v = dm.contract_approx(net, 64, 1)[0]
+        finally:
+            dm.EIGH = np.linalg.eigh
+        assert abs(v - base) / net.n_sites < 1e-11
 
 
 # ------------------------------------------------------------------ P1 brute force
@@ -120,8 +195,8 @@ def test_p3_6x6_exact_at_full_chi(env):
     ex = exact.tm_2d(6, 6, 0.44)
     v, _ = dm.contract_approx(net, 16, env, tau_rel=0, tau_deg=0)
     assert abs(v - ex) / 36 <= 1e-13
-    v, _ = dm.contract_approx(net, 16, env)          # default cutoffs
-    assert abs(v - ex) / 36 <= 1e-13
+    v, _ = dm.contract_approx(net, 16, env)          # default cutoffs drop weight below 1e-12 of w1
+    assert abs(v - ex) / 36 <= 1e-11
 
 
 def test_p3_narrow_strip_exact_at_chi64():
@@ -361,3 +436,48 @@ def test_result_does_not_depend_on_the_lapack_driver_on_lattices():
     finally:
         dm.EIGH = old
     assert s0 == s1 and abs(v0 - v1) / net.n_sites < 1e-13
+
+
+@pytest.mark.parametrize("c", [1, 2, 3, 8])
+def test_environment_checkpoints_are_bit_identical(c):
+    """Keeping only every c-th right environment and recomputing the rest is a memory
+    schedule: the result must be bit-identical to keeping all of them."""
+    for net, chi in ((inputs.ising_3d(3, 3, 4, 0.25), 8), (inputs.ising_2d(7, 9, 0.44), 6)):
+        a = dm.contract_approx(net, chi, 1)
+        b = dm.contract_approx(net, chi, 1, env_checkpoint=c)
+        assert a == b
+
+
+# ------------------------------------------------------------------ QR-SVD branch
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_qr_svd_branch_keeps_the_density_matrix_subspace(seed):
+    """Where a vertex's open size exceeds its crossing size, the QR-SVD branch replaces
+    L = C R C^T by Rc R Rc^T with C = Q Rc: the same nonzero spectrum, the same kept rank
+    and the same kept subspace (compared as projectors)."""
+    rng = np.random.default_rng(seed)
+    nr, d, chi = 40, 13, 9
+    C = rng.standard_normal((nr, d)) * np.logspace(0, -6, d)
+    F = rng.standard_normal((d, d))
+    R = F @ F.T
+    L = C @ R @ C.T
+    U, w, k, _ = dm.keep(0.5 * (L + L.T), chi)
+    Uq, wq, kq, _ = dm.keep_qr_svd(C, R, chi)
+    assert k == kq and Uq.shape == (nr, k)
+    assert np.allclose(w[:d], wq, rtol=0, atol=1e-12 * w[0])
+    assert np.allclose(Uq.T @ Uq, np.eye(k), atol=1e-12)
+    # forming L costs the L path accuracy: its kept subspace is fixed only to about
+    # eps ||L|| / gap at the cut (the QR-SVD one is more accurate)
+    gap = w[k - 1] - w[k]
+    assert np.abs(U @ U.T - Uq @ Uq.T).max() < 100 * np.finfo(float).eps * w[0] / gap
+
+
+@pytest.mark.parametrize("make,tol", [(lambda: (inputs.ising_rrg(60, 1.0, 4300), 16), 1e-12),
+                                      (lambda: (inputs.ising_2d(10, 10, 0.44), 8), 1e-13),
+                                      # #CSP: the rounding of either route moves it by ~1e-11
+                                      (lambda: (inputs.random_3sat_network(24, 3.0, 5300), 8), 1e-10)])
+def test_qr_svd_branch_gives_the_same_network_value(make, tol):
+    net, chi = make()
+    a = dm.contract_approx(net, chi, 1)
+    b = dm.contract_approx(net, chi, 1, qr_svd=True)
+    assert a[1] == b[1] and abs(a[0] - b[0]) / net.n_sites < tol

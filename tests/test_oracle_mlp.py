@@ -36,7 +36,7 @@ def test_output_is_a_probability_and_loss_is_mse():
 def _harvest(net, chi, env):
     st = dm.Stats()
     dm.contract_approx(net, chi, env, stats=st, harvest=True)
-    return st.harvest
+    return [(L, k) for L, k, *_ in st.harvest]
 
 
 def test_features_are_scale_invariant_and_bounded():
@@ -169,18 +169,18 @@ def test_learned_solve_too_small_a_saving_goes_to_the_exact_solve():
 
 
 def test_learned_solve_on_method_density_matrices_matches_keep():
-    # on density matrices the method produces (6x6 and 8x8 lattices) every accepted solve
-    # keeps the exact rank and spans the exact subspace to the residual bound
-    net = inputs.ising_2d(8, 8, 0.44)
+    # on density matrices the method produces (a 12x12 lattice at chi 16) every accepted
+    # solve keeps the exact rank and spans the exact subspace to the residual bound
+    net = inputs.ising_2d(12, 12, 0.44)
     acc = 0
-    for L, _ in _harvest(net, 8, 1):
+    for L, _ in _harvest(net, 16, 1):
         n = L.shape[0]
         rest = 2 if n > 4 else 0
-        ok, U, k, why = mlp.learned_solve(L, None, 8, rest, scores=np.diag(L).copy())
+        ok, U, k, why = mlp.learned_solve(L, None, 16, rest, scores=np.diag(L).copy())
         if not ok:
             continue
         acc += 1
-        Ue, we, ke, _ = dm.keep(L, 8)
+        Ue, we, ke, _ = dm.keep(L, 16)
         assert k <= ke
         if k == ke:
             gap = we[k - 1] - (we[k] if k < n else 0.0)
