@@ -69,21 +69,6 @@ def golden_errors(results, chis, envs):
     return errs
 
 
-def train_model(T):
-    """The warm-start MLP trained on rows the method harvests from density matrices of the
-    6x6 lattice (chi 4 and 16), 64x64 lattices at two inverse temperatures that are not in
-    the timed set, and a 4x4x4 cubic lattice (the 3D workload's single-workgroup size)."""
-    from paper_2406_09769_amd import inputs
-    ds = T.Dataset(600_000)
-    for net, chi in ((inputs.ising_2d(6, 6, 0.44), 4), (inputs.ising_2d(6, 6, 0.44), 16),
-                     (inputs.ising_2d(64, 64, 0.40), 32), (inputs.ising_2d(64, 64, 0.50), 32),
-                     (inputs.ising_3d(4, 4, 4, 0.2217), 16)):
-        T.tn_harvest(T.create_network(net), net.slices, chi, 1, ds)
-    m = T.Model(seed=7)
-    m.train(ds, steps=3000, batch=128, lr=3e-3, seed=11)
-    return m
-
-
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -246,7 +231,8 @@ def main():
     # 16-bit products resolve nothing below that (the FP32 sums inside each 16-bit matrix
     # instruction leave about 6e-8 of ||L||), and plain FP64 at the same cutoff is timed beside
     # them, so that the arithmetic is compared at equal method settings.
-    model = None if args.no_forms else train_model(T)
+    from paper_2406_09769_amd.learned import train_warm_start_model
+    model = None if args.no_forms else train_warm_start_model(T)
     form_list = [] if args.no_forms else [
         ("fp64", dict()),
         ("fp64_tau_rel_1e-10", dict(tau_rel=SPLIT_TAU_REL)),

@@ -94,7 +94,8 @@ typedef struct tn_dataset_s *tn_dataset;  /* harvested (features, leverage) rows
 typedef struct {
   int32_t precision;      /* tn_precision */
   int32_t eig;            /* tn_eig_mode */
-  double residual_tol;    /* learned mode: accepted max ||L x - theta x|| / theta_1 (1e-6) */
+  double residual_tol;    /* learned mode: accepted max ||L x - theta x|| / theta over the kept
+                             Ritz pairs (1e-6) */
   double tau_rel;         /* eigenvalues <= tau_rel * w1 are dropped */
   double tau_deg;         /* no cut where w_k - w_{k+1} <= tau_deg * w_k (see above) */
   void *hip_stream;       /* hipStream_t the work is queued on (NULL = null stream) */
@@ -103,6 +104,13 @@ typedef struct {
                              rows: 0 = built-in, k = 1..6 the k-th of 16x512/k8, 16x256/k16,
                              32x128/k32, 32x128/k16, 64x64/k32, 64x64/k16 (the autotuner's
                              choices, paper_2406_09769_amd/autotune.py) */
+  int32_t chunks;         /* > 1: the persistent launch of a batch runs as this many
+                             launches, each over the next part of every network's op list
+                             (eager launches, same results bit for bit); 0 or 1: one launch,
+                             replayed from a captured HIP graph */
+  void (*progress)(void *ctx, int32_t done, int32_t total); /* chunks > 1: called on the host
+                             after each part has finished (may be NULL) */
+  void *progress_ctx;     /* passed to progress */
 } tn_options;
 
 /* Result of one contraction. log_abs = ln|Z| (natural log), sign in {-1, 0, +1};
@@ -167,7 +175,7 @@ int tn_contract_approx_noalloc(tn_net net, const tn_path *path, int32_t max_rank
  * of a density matrix L that a small MLP ranks highest, computed row by row from
  * bond-local features (diagonal and row weight of L, position of the row's bond and
  * leaf index, size). It accepts the Ritz vectors when every kept residual satisfies
- * ||L x - theta x|| <= residual_tol * theta_1 and otherwise falls back to the exact
+ * ||L x - theta x|| <= residual_tol * theta and otherwise falls back to the exact
  * solve (tn_result.n_learned counts the accepted warm starts). Training data come
  * from the method itself: tn_harvest runs an exact
  * contraction and records, for every row of every density matrix, its 8 features

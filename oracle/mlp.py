@@ -140,7 +140,8 @@ def warm_subspace(L, scores, p, iters):
 # ------------------------------------------------------------------ the learned solve and its acceptance rule
 
 DROP_REL = 1e-26      # a start column whose new part has squared norm <= DROP_REL * its own is dropped
-TAIL_REL = 1e-11      # weight allowed outside the subspace when the cutoff (not chi) decides the rank
+TAIL_REL = 1e-13      # weight allowed outside the subspace when the cutoff (not chi) decides the rank:
+                      # the rank rule's floor at the default cutoff (0.1 x 1e-12)
 FRO_SLACK = 1e-13     # relative rounding allowance of the Frobenius-norm bound
 REASONS = ("size", "dependent", "cut", "residual")
 
@@ -196,9 +197,10 @@ def learned_solve(L, w, chi, rest, residual_tol=1e-6, tau_rel=1e-12, tau_deg=0.1
     3. Bound the largest eigenvalue of L on the complement of span(V) by
        b = min(t, f) with t = tr(L) - tr(H) and f = sqrt(max(0, ||L||^2 - 2||W||^2 +
        ||H||^2) + FRO_SLACK * ||L||^2) (Frobenius norms). Accept when the weight outside
-       is negligible, t <= TAIL_REL * theta_1, or when b cannot move a cut that chi
+       is below the rank rule's floor, t <= floor * theta_1, or when b cannot move a cut that chi
        decides (k = min(chi, n), b <= theta_k / 2 and b < (1 - tau_deg) theta_k),
-       and every kept Ritz pair has ||W y - theta V y|| <= residual_tol * theta_1.
+       and every kept Ritz pair has ||W y - theta V y|| <= residual_tol * theta (relative
+       to its own Ritz value: the smallest kept directions must be resolved too).
        Else V <- orth_drop(W) and repeat.
 
     scores, when given, replaces the MLP's row scores (tests of the rule itself).
@@ -239,11 +241,11 @@ def learned_solve(L, w, chi, rest, residual_tol=1e-6, tau_rel=1e-12, tau_deg=0.1
         ok = k >= 1 and th1 > 0
         if ok:
             thk = thp[k - 1]
-            ok = t <= TAIL_REL * th1 or (k == kmax and b <= 0.5 * thk and b < thk - tau_deg * thk)
+            ok = t <= floor * th1 or (k == kmax and b <= 0.5 * thk and b < thk - tau_deg * thk)
         if ok:
             Xr = V @ Y[:, :k]
             R = W @ Y[:, :k] - Xr * th[:k]
-            if np.linalg.norm(R, axis=0).max() <= residual_tol * th1:
+            if (np.linalg.norm(R, axis=0) / th[:k]).max() <= residual_tol:
                 return True, Xr, k, None
             reason = "residual"
         else:

@@ -381,6 +381,7 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
     nd[q].dyn = reinterpret_cast<int32_t *>(nets[i]->d_ws + plans[i]->plan.dyn_off);
   }
   hipGraphExec_t persist = nullptr;
+  const bool parts = o.chunks > 1 && n_persist > 0;
   if (n_persist > 0) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -401,7 +402,9 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
     const int np = int(n_persist);
     key_put(key, &np, sizeof(np));
     auto it = bc.execs.find(key);
-    if (it == bc.execs.end()) {
+    if (parts) {
+      // chunked: eager launches over parts of every op list (no graph)
+    } else if (it == bc.execs.end()) {
       if (bc.execs.size() >= kMaxGraphsPerPlan) {
         HIP_TRY(hipStreamSynchronize(st));
         for (auto &kv : bc.execs) (void)hipGraphExecDestroy(kv.second);
@@ -417,8 +420,10 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
       if (rc != TN_OK) return rc;
       it = bc.execs.emplace(std::move(key), ge).first;
     }
-    persist = it->second;
-    HIP_TRY(hipMemcpyAsync(bc.d_nd, nd.data(), n_persist * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
+    if (!parts) {
+      persist = it->second;
+      HIP_TRY(hipMemcpyAsync(bc.d_nd, nd.data(), n_persist * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
+    }
   }
   struct Events {                          // released on every return path
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -431,6 +436,22 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
   HIP_TRY(hipEventCreate(&ev.e1));
   HIP_TRY(hipEventRecord(ev.e0, st));
   if (persist) HIP_TRY(hipGraphLaunch(persist, st));
+  if (parts) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    tn::NetDev *d_nd = g_batch[dev].d_nd;
+    std::vector<tn::NetDev> part(nd.begin(), nd.begin() + long(n_persist));
+    for (int32_t c = 0; c < o.chunks; ++c) {
+      for (size_t q = 0; q < n_persist; ++q) {
+        part[q].op_begin = nd[q].n_ops * c / o.chunks;
+        part[q].op_end = nd[q].n_ops * (c + 1) / o.chunks;
+      }
+      HIP_TRY(hipMemcpyAsync(d_nd, part.data(), n_persist * sizeof(tn::NetDev), hipMemcpyHostToDevice, st));
+      HIP_TRY(tn::launch_interp_parts(d_nd, int(n_persist), kp, st));
+      HIP_TRY(hipStreamSynchronize(st));   // the next part's descriptors overwrite these
+      if (o.progress) o.progress(o.progress_ctx, c + 1, o.chunks);
+    }
+  }
   for (size_t q = n_persist; q < n; ++q) {
     const int rc = run_stepwise(nets[order[q]], plans[order[q]], nd[q], kp, st);
     if (rc != TN_OK) {
@@ -520,6 +541,7 @@ static int prepare_options(const tn_options *opt, tn_options &o, tn::KeepParams 
   if (o.eig != TN_EIG_EXACT && o.eig != TN_EIG_LEARNED) return fail(TN_EINVAL, "unknown eigensolve mode");
   if (o.eig == TN_EIG_LEARNED && !o.model) return fail(TN_EINVAL, "learned eigensolve needs a model");
   if (o.eig == TN_EIG_LEARNED && !(o.residual_tol > 0)) return fail(TN_EINVAL, "residual_tol must be > 0");
+  if (o.chunks < 0) return fail(TN_EINVAL, "chunks must be >= 0");
   if (!(o.tau_rel >= 0) || !(o.tau_deg >= 0)) return fail(TN_EINVAL, "tau_rel and tau_deg must be >= 0");
   for (int c = 0; c < 3; ++c)
     if (o.gemm_config[c] < 0 || o.gemm_config[c] > tn::kGemmConfigs) return fail(TN_EINVAL, "gemm_config out of range");

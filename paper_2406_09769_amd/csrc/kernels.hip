@@ -1424,13 +1424,16 @@ __device__ void sym_times(const double *A, int pa, const double *V, int n, int p
 // b = min(t, f): t = tr(L) - tr(H) = tr(C) (C is PSD when L is), and
 // f = sqrt(||L||^2 - 2||W||^2 + ||H||^2 + slack) = ||C||_F (Frobenius identities of
 // the 2x2 block split; the slack covers their rounding). The result is accepted when
-//  * the weight off span(V) is negligible, t <= kLearnedTail * theta_1, or the rank is
-//    capped by max_rank and b cannot move that cut (b <= theta_k / 2 and
-//    b < (1 - tau_deg) theta_k), and
-//  * every kept Ritz pair has ||L x - theta x|| <= residual_tol * theta_1.
+//  * the weight off span(V) is below the floor of the rank rule, t <= floor * theta_1
+//    (so no eigenvalue the exact rule could keep lies outside), or the rank is capped by
+//    max_rank and b cannot move that cut (b <= theta_k / 2 and b < (1 - tau_deg) theta_k),
+//    and
+//  * every kept Ritz pair has ||L x - theta x|| <= residual_tol * theta, relative to its
+//    own Ritz value: the smallest kept directions carry weight far below theta_1 and
+//    later partitions can amplify them (#CSP networks), so they must be resolved too.
 // Returns true with U written and the kept rank set; false leaves everything for the
 // exact solve (the reason is counted in sc->rej).
-constexpr double kLearnedTail = 1e-11, kFroSlack = 1e-13;
+constexpr double kFroSlack = 1e-13;
 __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
                             double *lds, int n, int ld, int ucols) {
   const int tid = threadIdx.x;
@@ -1529,7 +1532,7 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
     bool cut_ok = k >= 1 && th1 > 0.0;
     if (cut_ok) {
       const double thk = E.wsrt[k - 1];
-      cut_ok = tail <= kLearnedTail * th1 || (k == kmax && bnd <= 0.5 * thk && bnd < thk - kp.tau_deg * thk);
+      cut_ok = tail <= kp.floor * th1 || (k == kmax && bnd <= 0.5 * thk && bnd < thk - kp.tau_deg * thk);
     }
     if (cut_ok) {
       back_transform(E, k);                              // Y columns (p x k) in E.A
@@ -1547,15 +1550,15 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
         U[int64_t(j) * ld + i] = x;
       }
       __syncthreads();
-      double rmax = 0.0;
-      for (int j = tid; j < k; j += kThreads) rmax = fmax(rmax, sqrt(G[j]));
+      double rmax = 0.0;                           // largest residual relative to its Ritz value
+      for (int j = tid; j < k; j += kThreads) rmax = fmax(rmax, sqrt(G[j]) / E.wsrt[j]);
       rmax = block_max(rmax, red);
       lap(3);
-      if (rmax <= kp.residual_tol * th1) {
+      if (rmax <= kp.residual_tol) {
         if (tid == 0) {
           dyn[op.out_dyn] = k;
           sc->n_learned += 1;
-          sc->max_resid = fmax(sc->max_resid, rmax / th1);
+          sc->max_resid = fmax(sc->max_resid, rmax);
           sc->eig_flops += 9LL * p * p * p + 4LL * n * n * p * (it + 1);
         }
         __syncthreads();
@@ -1663,10 +1666,25 @@ __device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__r
   double *X = lds;                                   // m x pitch
   double *Qb = X + m * pitch;                        // kk x m: column t of Q at Qb[t*m + i]
   double *vdiag = Qb + kk * m, *bet = vdiag + kQrMaxCols, *rdiag = bet + kQrMaxCols;
+  // offsets resolved once: C's row and column offsets, and where each valid row of Q and
+  // column of R is stored (the gathers then need one load per element)
+  int64_t *roff = reinterpret_cast<int64_t *>(rdiag + kQrMaxCols), *coff = roff + kQrMaxRows;
+  int32_t *qpos = reinterpret_cast<int32_t *>(coff + kQrMaxCols), *rpos = qpos + kQrMaxRows;
+  for (int i = tid; i < m; i += kThreads) {
+    const int32_t s = box_conv(op.bm, i);
+    roff[i] = map_off(tab, op.am, s);
+    qpos[i] = s;
+  }
+  for (int j = tid; j < c; j += kThreads) {
+    const int32_t s = box_conv(op.bnb, j);
+    coff[j] = map_off(tab, op.bn, s);
+    rpos[j] = s;
+  }
+  __syncthreads();
   const double *Cg = ws + op.a;
   for (int e = tid; e < m * c; e += kThreads) {
     const int i = e / c, j = e % c;
-    X[i * pitch + j] = Cg[map_off(tab, op.am, box_conv(op.bm, i)) + map_off(tab, op.bn, box_conv(op.bnb, j))];
+    X[i * pitch + j] = Cg[roff[i] + coff[j]];
   }
   __syncthreads();
   for (int j = 0; j < kk; ++j) {
@@ -1719,11 +1737,11 @@ __device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__r
   const int64_t ldq = op.count, ldr = op.bn.n;
   for (int e = tid; e < kk * m; e += kThreads) {
     const int q = e / m, i = e % m;
-    Q[q * ldq + box_conv(op.bm, i)] = Qb[q * m + i];
+    Q[q * ldq + qpos[i]] = Qb[q * m + i];
   }
   for (int e = tid; e < kk * c; e += kThreads) {
     const int q = e / c, j = e % c;
-    R[q * ldr + box_conv(op.bnb, j)] = j > q ? X[q * pitch + j] : (j == q ? rdiag[q] : 0.0);
+    R[q * ldr + rpos[j]] = j > q ? X[q * pitch + j] : (j == q ? rdiag[q] : 0.0);
   }
   if (tid == 0) {
     dyn[op.out_dyn] = kk;
@@ -1776,6 +1794,10 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
   if (tid < kScWords) reinterpret_cast<long long *>(&s_sc)[tid] = reinterpret_cast<const long long *>(g_sc)[tid];
   __syncthreads();
   nd.sc = &s_sc;
+  if (first < 0) {                    // a part of a chunked batch: the descriptor's range
+    first = nd.op_begin;
+    last = nd.op_end;
+  }
   const int64_t end = last < 0 ? nd.n_ops : last;
   // the next op's words are loaded while the current op runs: the op arrays are read once
   // per launch, so each descriptor would otherwise cost a full memory round trip
@@ -2196,6 +2218,11 @@ __global__ __launch_bounds__(kThreads) void rescale_apply_kernel(const NetDev *_
 
 hipError_t launch_interp(const NetDev *nets_dev, int n_nets, const KeepParams &kp, hipStream_t stream) {
   hipLaunchKernelGGL(interp_kernel, dim3(n_nets), dim3(kThreads), 0, stream, nets_dev, kp, int64_t(0), int64_t(-1));
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_parts(const NetDev *nets_dev, int n_nets, const KeepParams &kp, hipStream_t stream) {
+  hipLaunchKernelGGL(interp_kernel, dim3(n_nets), dim3(kThreads), 0, stream, nets_dev, kp, int64_t(-1), int64_t(-1));
   return hipGetLastError();
 }
 

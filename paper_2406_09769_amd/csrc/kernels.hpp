@@ -15,6 +15,7 @@ struct NetDev {
   const double *cst;
   NetScalars *sc;
   int32_t *dyn;      // kept-rank slots (inside the workspace)
+  int64_t op_begin = 0, op_end = -1;   // ops a chunked launch runs (first < 0 in the launch)
 };
 
 // Rank rule of the eigensolve: drop w <= tau_rel*w1; never cut where
@@ -23,7 +24,7 @@ struct KeepParams {
   double tau_rel;
   double tau_deg;
   double floor;
-  double residual_tol;     // learned mode: accepted max ||L x - theta x|| / theta_1
+  double residual_tol;     // learned mode: accepted max ||L x - theta x|| / theta (kept pairs)
   const float *model;      // learned mode: MLP weights, or null for the exact solve
   float *hx, *hy;          // harvest: feature rows (8 floats) and leverage targets, or null
   int *hcount;             // harvest: rows written so far (atomic)
@@ -48,6 +49,9 @@ hipError_t launch_mlp_train(float *w, float *m, float *v, const float *X, const 
                             float *grad_out, hipStream_t stream);
 
 hipError_t launch_interp(const NetDev *nets_dev, int n_nets, const KeepParams &kp, hipStream_t stream);
+// The same over each network's ops [op_begin, op_end) of its descriptor (a part of a
+// chunked batch; the network's scalars are written back at the end of every part).
+hipError_t launch_interp_parts(const NetDev *nets_dev, int n_nets, const KeepParams &kp, hipStream_t stream);
 
 // Precision a GEMM op runs in under kp: kp.split for the ops the split applies to, else 0.
 __host__ __device__ inline int op_split(const KeepParams &kp, int32_t op_flags) {

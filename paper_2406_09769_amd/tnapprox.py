@@ -40,10 +40,14 @@ class tn_path(C.Structure):
                 ("slice_vertices", C.POINTER(C.c_int32))]
 
 
+PROGRESS = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32)
+
+
 class tn_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eig", C.c_int32), ("residual_tol", C.c_double),
                 ("tau_rel", C.c_double), ("tau_deg", C.c_double), ("hip_stream", C.c_void_p),
-                ("model", C.c_void_p), ("gemm_config", C.c_int32 * 3)]
+                ("model", C.c_void_p), ("gemm_config", C.c_int32 * 3), ("chunks", C.c_int32),
+                ("progress", PROGRESS), ("progress_ctx", C.c_void_p)]
 
 
 class tn_result(C.Structure):
@@ -147,11 +151,17 @@ class _PathArgs:
                             self.flat.ctypes.data_as(C.POINTER(C.c_int32)))
 
 
+_LIVE = []   # the progress callback of the call in flight (kept alive across it)
+
+
 def _options(precision=TN_FP64, eig=TN_EIG_EXACT, residual_tol=1e-6, tau_rel=1e-12, tau_deg=0.1,
-             stream=None, model=None, gemm_config=(0, 0, 0)):
+             stream=None, model=None, gemm_config=(0, 0, 0), chunks=0, progress=None):
+    """progress: a Python callable (done, total) called after each part when chunks > 1."""
+    cb = PROGRESS(lambda ctx, done, total: progress(int(done), int(total))) if progress else PROGRESS()
+    _LIVE[:] = [cb]
     return tn_options(int(precision), int(eig), float(residual_tol), float(tau_rel), float(tau_deg),
                       C.c_void_p(stream) if stream else None, model.ptr if model is not None else None,
-                      (C.c_int32 * 3)(*[int(x) for x in gemm_config]))
+                      (C.c_int32 * 3)(*[int(x) for x in gemm_config]), int(chunks), cb, None)
 
 
 @dataclass

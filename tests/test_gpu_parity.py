@@ -223,3 +223,18 @@ def test_persistent_launch_graph_replays_match_eager_launches(T):
         assert again.log_abs == eager[rep].log_abs
     sub = T.tn_contract_approx_batch(hs[:2], [n.slices for n in nets[:2]], chis[:2], envs[:2])
     assert [r.log_abs for r in sub] == [a.log_abs for a in eager[:2]]
+
+
+def test_batch_in_parts_matches_one_launch(T):
+    """A batch run as several launches over consecutive parts of every network's op list
+    (tn_options.chunks) gives the one-launch results bit for bit and reports each part."""
+    nets = [inputs.ising_2d(12, 10, b) for b in (0.35, 0.5)] + [inputs.ising_rrg(40, 1.0, 4210)]
+    chis, envs = [8, 12, 16], [1, 2, 1]
+    hs = [T.create_network(n) for n in nets]
+    one = T.tn_contract_approx_batch(hs, [n.slices for n in nets], chis, envs)
+    seen = []
+    parts = T.tn_contract_approx_batch(hs, [n.slices for n in nets], chis, envs, chunks=5,
+                                       progress=lambda d, t: seen.append((d, t)))
+    assert seen == [(d, 5) for d in range(1, 6)]
+    for a, b in zip(one, parts):
+        assert a.log_abs == b.log_abs and a.sign == b.sign and a.flops == b.flops
