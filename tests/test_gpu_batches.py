@@ -88,6 +88,13 @@ def test_csp_batch_matches_oracle(T):
           f"{worst:.2f}", flush=True)
 
 
+# The 150-variable batches run for minutes; their progress lines only reach a terminal
+# with pytest -s, and a run that prints nothing for minutes is taken for hung. They run
+# when TN_LONG_GPU_TESTS=1 (with -s).
+LONG = pytest.mark.skipif(os.environ.get("TN_LONG_GPU_TESTS") != "1",
+                          reason="minutes of GPU time with no output under capture; set TN_LONG_GPU_TESTS=1 and use -s")
+
+
 def _progress(done, total):
     print(f"  part {done}/{total} done", flush=True)
 
@@ -102,6 +109,7 @@ def w5_full(T):
 
 
 
+@LONG
 def test_csp_full_size_batch_exact(T, w5_full):
     gold, nets, hs = w5_full
     print("3-SAT #CSP: 32 formulas, n 150, m 450, chi 32, one batch in 16 parts, exact eigensolve", flush=True)
@@ -111,6 +119,7 @@ def test_csp_full_size_batch_exact(T, w5_full):
           f"{worst:.2f}", flush=True)
 
 
+@LONG
 def test_csp_full_size_batch_learned_vs_exact(T, w5_full):
     """The learned warm start on the 150-variable formulas (MLP trained on density matrices
     of the lattice workloads, exact solve as fallback when a residual exceeds 1e-6): the same
