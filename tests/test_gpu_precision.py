@@ -126,3 +126,25 @@ def test_w3_full_size_precision_form(T, precision, tau_rel):
         bound = BOUND if g["beta"] < 0.25 else BOUND_ILL     # beta 0.25: ordered phase
         assert r.sign == g["sign"] and d <= bound
         del h
+
+
+def test_w4_random_graphs_in_the_split_form(T):
+    """The 64 signed random 3-regular graphs (chi 64) in one launch with BF16 x3 environment
+    and density-matrix contractions (FP32 sums inside each matrix instruction). Their kept
+    spectra reach 1e-12 of the largest eigenvalue, far below the split forms' noise floor
+    (about 6e-8 ||L||): the split form does not resolve these networks (measured worst
+    2.4e-4 per site, median 1.4e-7, 4 of 64 within 1e-8). This is a measurement, not a
+    parity claim: every graph's error is printed, and the assertion only guards against a
+    broken run (signs, and 1e-3 per site)."""
+    gold = json.load(open(os.path.join(HERE, "golden", "w4_oracle.json")))["rows"]
+    nets = inputs.rrg_batch(64)
+    hs = [T.create_network(n) for n in nets]
+    rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], 64, 1, precision=T.TN_SPLIT_BF16X3)
+    errs = []
+    for net, g, r in zip(nets, gold, rs):
+        assert net.name == g["name"] and r.sign == g["sign"]
+        errs.append(abs(r.log_abs - g["log_abs"]) / net.n_sites)
+    print(f"64 graphs, BF16 x3: kernel {rs[0].seconds:.2f} s, worst |dlnZ|/N {max(errs):.2e}, median "
+          f"{sorted(errs)[32]:.2e}, within 1e-8: {sum(e <= BOUND for e in errs)}/64; per graph "
+          f"{[f'{e:.1e}' for e in errs]}", flush=True)
+    assert max(errs) <= BOUND_ILL
