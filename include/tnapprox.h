@@ -35,7 +35,8 @@ enum {
   TN_EDEVICE = 3,   /* a HIP runtime call failed, or no usable gfx950 device */
   TN_ENUMERIC = 4,  /* an input tensor holds a non-finite value */
   TN_EUNSUPPORTED = 5 /* valid input outside this build's limits (e.g. a density
-                         matrix larger than 128 x 128) */
+                         matrix larger than 512 x 512, or an intermediate of 2^31
+                         elements or more) */
 };
 
 /* One input tensor: host memory, row-major FP64, dims[order]. order 0 is a scalar. */
@@ -248,7 +249,8 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
 
 /* U (n x ucols, row-major) = the kept leading eigenvectors of (L + L^T)/2 (n x n),
  * zero columns past the kept rank, under opt's tau_rel and tau_deg (NULL: defaults).
- * n <= 128. rest = 0: plain rows; rest > 0: rows are (bond, leaf) pairs with leaf
+ * n <= 512 (orders above 128 are solved in global scratch). rest = 0: plain rows;
+ * rest > 0: rows are (bond, leaf) pairs with leaf
  * dimension rest (must divide n), the layout the learned warm start reads its row
  * features from. With opt->eig = TN_EIG_LEARNED and opt->model set, the warm start is
  * tried first, as in a contraction. stats (8 entries, may be NULL): no eigenvalue

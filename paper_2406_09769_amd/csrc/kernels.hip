@@ -743,14 +743,20 @@ struct EigWs {          // LDS work area of one solve of order n
 };
 
 __host__ __device__ constexpr int eig_lds_doubles(int n) { return n * (n + 1) + 14 * n + (n + 1) / 2 + 8 + 24; }
-static_assert(eig_lds_doubles(128) <= kLdsDoubles, "the largest density matrix fits LDS");
+static_assert(eig_lds_doubles(128) <= kLdsDoubles, "a density matrix of order 128 fits LDS");
+// Larger density matrices (up to order kMaxEigDim) keep the matrix and Z in the op's global
+// scratch and only the solver's vectors in LDS.
+static_assert(eig_lds_doubles(kMaxEigDim) - kMaxEigDim * (kMaxEigDim + 1) <= kLdsDoubles,
+              "the solver's vectors of the largest density matrix fit LDS");
 
-__device__ EigWs eig_ws(double *base, int n, double *hv) {
+// Work area of one solve: the matrix at A when given (global scratch), else at the start
+// of base; the vectors follow in base.
+__device__ EigWs eig_ws(double *base, int n, double *hv, double *A = nullptr) {
   EigWs E;
   E.n = n;
   E.pa = n + 1;                        // odd pitch: conflict-free row access
-  E.A = base;
-  E.vv = base + n * E.pa;
+  E.A = A ? A : base;
+  E.vv = A ? base : base + n * E.pa;
   E.pp = E.vv + n;
   E.ww = E.pp + n;
   E.dd = E.ww + n;
@@ -1044,8 +1050,7 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
     for (int i = lane; i < n; i += 64) tn = fmax(tn, fmax(fabs(de[i].x), 2.0 * fabs(de[i].y)));
     efloor = kEps * wave_max(tn);
   }
-  const int crow = tid - 64;                        // consumer row
-  const bool own = wave > 0 && crow < n;
+  const int crow = tid - 64;                        // first consumer row
   for (int b = 0;; b ^= 1) {
     if (wave == 0) {
       int m = -1;
@@ -1108,19 +1113,21 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
     __syncthreads();
     const int m = meta[2 * b], cnt = meta[2 * b + 1];
     if (cnt < 0) break;
-    if (own && cnt > 0) {                            // apply the iteration's rotations to row crow
+    if (wave > 0 && cnt > 0) {                       // apply the iteration's rotations to rows crow
       const Pair *rb = rot + n * b;
-      double zc = Z[m * n + crow];                   // current value of column i+1
-      double zn = Z[(m - 1) * n + crow];             // column i, fetched one step ahead
-      for (int j = 0; j < cnt; ++j) {
-        const int i = m - 1 - j;
-        const double zi = zn;
-        if (j + 1 < cnt) zn = Z[(i - 1) * n + crow];
-        const Pair cs = rb[j];
-        Z[(i + 1) * n + crow] = cs.y * zi + cs.x * zc;
-        zc = cs.x * zi - cs.y * zc;
+      for (int row = crow; row < n; row += kThreads - 64) {
+        double zc = Z[m * n + row];                  // current value of column i+1
+        double zn = Z[(m - 1) * n + row];            // column i, fetched one step ahead
+        for (int j = 0; j < cnt; ++j) {
+          const int i = m - 1 - j;
+          const double zi = zn;
+          if (j + 1 < cnt) zn = Z[(i - 1) * n + row];
+          const Pair cs = rb[j];
+          Z[(i + 1) * n + row] = cs.y * zi + cs.x * zc;
+          zc = cs.x * zi - cs.y * zc;
+        }
+        Z[(m - cnt) * n + row] = zc;
       }
-      Z[(m - cnt) * n + crow] = zc;
     }
   }
   __syncthreads();
@@ -1609,12 +1616,16 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
   const int n = box_eff(op.bm);            // runtime dimension: the valid leading block
   const int ucols = op.K;
   const int tid = threadIdx.x;
-  const bool warm = !(op.flags & F_NO_WARM);
+  // a matrix too large for LDS (order above about 135) is solved in the op's global
+  // scratch: reflectors first (n^2 + n doubles), then the matrix and Z (n (n + 1))
+  const bool big = eig_lds_doubles(n) > kLdsDoubles;
+  const bool warm = !(op.flags & F_NO_WARM) && !big;
   if (kp.model && warm && eig_learned(op, ws, dyn, kp, sc, lds, n, ld, ucols)) return;
   // the reflectors stay in LDS when they fit beside the work area (n up to about 90): the
   // reduction's writes and the back-transformation's reads then never wait on memory
-  const bool hv_lds = eig_lds_doubles(n) + n * n + n <= kLdsDoubles;
-  EigWs E = eig_ws(lds, n, hv_lds ? lds + eig_lds_doubles(n) : ws + op.b);
+  const bool hv_lds = !big && eig_lds_doubles(n) + n * n + n <= kLdsDoubles;
+  EigWs E = big ? eig_ws(lds, n, ws + op.b, ws + op.b + (int64_t(n) * n + n))
+                : eig_ws(lds, n, hv_lds ? lds + eig_lds_doubles(n) : ws + op.b);
   const double *L = ws + op.a;
   long long t0 = wall_clock64();
   for (int e = tid; e < n * n; e += kThreads) {

@@ -868,7 +868,8 @@ std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupp
         if (std::find(rows.begin(), rows.end(), C.lab[i]) != rows.end()) nr *= C.dim[i];
       if (nr > kMaxEigDim) {
         *unsupported = true;
-        return "density matrix of dimension " + std::to_string(nr) + " exceeds the supported 128";
+        return "density matrix of dimension " + std::to_string(nr) + " exceeds the supported " +
+               std::to_string(kMaxEigDim);
       }
       int64_t ucols = std::min<int64_t>({int64_t(a.chi), nr, xdim(k)});
       int64_t bond = B.fresh();

@@ -50,6 +50,5 @@ struct PlanArgs {
 // beyond the supported dimension sets *unsupported.
 std::string make_plan(const Graph &g, const PlanArgs &a, Plan &out, bool *unsupported);
 
-constexpr int32_t kMaxEigDim = 128;
 
 }  // namespace tn

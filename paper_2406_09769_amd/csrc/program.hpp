@@ -21,6 +21,10 @@ enum OpKind : int32_t {
                    // q = min(rows, cols) written to slot out_dyn
 };
 
+// Largest density matrix the eigensolve takes (orders above 128 are solved in global
+// scratch, the rest in LDS).
+constexpr int32_t kMaxEigDim = 512;
+
 // Largest C the QR-SVD branch factors in one workgroup's LDS: rows x cols.
 constexpr int kQrMaxRows = 128;
 constexpr int kQrMaxCols = 64;

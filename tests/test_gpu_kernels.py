@@ -43,7 +43,8 @@ def _psd(n, spectrum, seed):
     return q @ np.diag(spectrum) @ q.T
 
 
-@pytest.mark.parametrize("n", [2, 3, 4, 7, 15, 16, 17, 31, 33, 48, 63, 64, 65, 97, 98, 99, 127, 128])
+@pytest.mark.parametrize("n", [2, 3, 4, 7, 15, 16, 17, 31, 33, 48, 63, 64, 65, 97, 98, 99, 127, 128,
+                               129, 135, 136, 193, 256, 257, 384, 511, 512])   # above 135: global scratch
 def test_eig_subspace_and_rank_match_oracle(T, n):
     rng = np.random.default_rng(n)
     w = np.sort(np.exp(-rng.uniform(0, 30, n)))[::-1]

@@ -238,3 +238,24 @@ def test_batch_in_parts_matches_one_launch(T):
     assert seen == [(d, 5) for d in range(1, 6)]
     for a, b in zip(one, parts):
         assert a.log_abs == b.log_abs and a.sign == b.sign and a.flops == b.flops
+
+
+@pytest.mark.parametrize("lz", [4, 8])
+def test_4x4_slab_exact_at_full_rank(T, lz):
+    """A 4x4 plane has 16 leaves of dimension 2, so rank 256 is the full bond dimension and
+    the method is exact (density matrices of order up to 512, solved in global scratch).
+    Against the slab transfer matrix (tests/golden/exact_values.json): to rounding with the
+    cutoffs off, and to the weight the default cutoff drops otherwise."""
+    gold = json.load(open(os.path.join(HERE, "golden", "exact_values.json")))
+    (g,) = [r for r in gold["ising3d"] if (r["lz"], r["ly"], r["lx"], r["beta"]) == (lz, 4, 4, 0.2217)]
+    net = inputs.ising_3d(lz, 4, 4, 0.2217)
+    h = T.create_network(net)
+    st = T.tn_plan_stats(h, net.slices, 256, 1)
+    assert st["max_eig_dim"] > 128
+    r0 = T.tn_contract_approx(h, net.slices, 256, 1, tau_rel=0.0, tau_deg=0.0)
+    r = T.tn_contract_approx(h, net.slices, 256, 1)
+    e0, e = abs(r0.log_abs - g["log_z"]) / net.n_sites, abs(r.log_abs - g["log_z"]) / net.n_sites
+    print(f"4x4x{lz} slab chi 256: largest density matrix {st['max_eig_dim']}, {st['n_eig']} eigensolves, "
+          f"|dlnZ|/N {e0:.2e} (cutoffs off, {r0.seconds:.2f} s), {e:.2e} (default, {r.seconds:.2f} s)", flush=True)
+    assert r0.sign == 1 and e0 <= 1e-12
+    assert r.sign == 1 and e <= 1e-10
