@@ -90,19 +90,19 @@ def cpu_baseline(sample: int):
     except Exception:
         threadpool_limits = None
         threads = os.cpu_count()
-    picks = []
     betas = inputs.w2_betas()
-    for i in range(sample):
-        chi, env = GROUPS[i % len(GROUPS)]
-        picks.append((chi, env, betas[(3 * i + 3) % len(betas)]))
+    full = [(chi, env, b) for chi, env in GROUPS for b in betas]      # the step's 32 networks
+    sample = min(sample, len(full))
+    picks = [full[(i * len(full)) // sample] for i in range(sample)]   # spread over the step
     t0 = time.perf_counter()
     for chi, env, b in picks:
         dm.contract_approx(inputs.ising_2d(64, 64, b), chi, env)
     dt = time.perf_counter() - t0
     out = {"value": len(picks) / dt, "unit": "networks/s", "cores": int(threads), "kind": "oracle",
            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
-           "sample": f"{len(picks)} of the 32 networks, one per (chi, env) in turn at betas "
-                     f"{sorted(set(round(p[2], 4) for p in picks))}; {dt:.1f} s on the host"}
+           "sample": (f"all 32 networks of the step" if len(picks) == len(full) else
+                      f"{len(picks)} of the 32 networks (chi, env, beta): "
+                      f"{[(c, e, round(b, 4)) for c, e, b in picks]}") + f"; {dt:.1f} s on the host"}
     if threadpool_limits is not None:
         with threadpool_limits(limits=1):
             t1 = time.perf_counter()
@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=8, help="networks timed in the CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=32, help="networks timed in the CPU oracle (0 = skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the runs of the other forms")
     ap.add_argument("--form-reps", type=int, default=5, help="timed launches per form (median)")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM block autotuner (built-in shapes)")
