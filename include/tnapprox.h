@@ -81,6 +81,13 @@ typedef enum {
   TN_EIG_LEARNED = 1    /* MLP warm start + subspace iteration, exact solve as fallback */
 } tn_eig_mode;
 
+typedef enum {
+  TN_TRIDIAG_AUTO = 0,  /* tridiagonal eigensolve by divide and conquer for density matrices
+                           of order up to 64 (Cuppen's tearing, eigenvectors from the roots by
+                           the Loewner formula of Gu and Eisenstat), implicit QL above */
+  TN_TRIDIAG_QL = 1     /* implicit QL with Wilkinson shifts for every order */
+} tn_tridiag;
+
 typedef struct tn_model_s *tn_model;      /* warm-start MLP weights on the device */
 typedef struct tn_dataset_s *tn_dataset;  /* harvested (features, leverage) rows on the device */
 
@@ -112,6 +119,9 @@ typedef struct {
   void (*progress)(void *ctx, int32_t done, int32_t total); /* chunks > 1: called on the host
                              after each part has finished (may be NULL) */
   void *progress_ctx;     /* passed to progress */
+  int32_t tridiag;        /* tn_tridiag: solver of the tridiagonal eigenproblem in the exact
+                             eigensolve (both reach the accuracy of a backward-stable FP64
+                             solve; the kept subspaces agree to rounding) */
 } tn_options;
 
 /* Result of one contraction. log_abs = ln|Z| (natural log), sign in {-1, 0, +1};

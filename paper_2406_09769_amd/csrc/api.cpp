@@ -264,6 +264,7 @@ std::vector<char> kp_key(const tn::KeepParams &kp) {
   key_put(key, &kp.residual_tol, 8); key_put(key, &kp.model, sizeof(kp.model)); key_put(key, &kp.hx, sizeof(kp.hx));
   key_put(key, &kp.hy, sizeof(kp.hy)); key_put(key, &kp.hcount, sizeof(kp.hcount)); key_put(key, &kp.hcap, 8);
   key_put(key, &kp.split, 4); key_put(key, &kp.split_all, 4); key_put(key, kp.gemm_cfg, 12);
+  key_put(key, &kp.tridiag_ql, 4);
   return key;
 }
 
@@ -369,6 +370,13 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
   std::vector<tn::NetDev> nd(n);
   tn::NetScalars init{};
   init.sign = 1;
+  struct SyncOnError {                     // an early return waits for the work already queued
+    hipStream_t st;                        // (declared after the host buffers it protects)
+    bool done = false;
+    ~SyncOnError() {
+      if (!done) (void)hipStreamSynchronize(st);
+    }
+  } pending{st};
   for (size_t q = 0; q < n; ++q) {
     const size_t i = order[q];
     HIP_TRY(hipMemcpyAsync(nets[i]->d_sc, &init, sizeof(init), hipMemcpyHostToDevice, st));
@@ -454,13 +462,11 @@ int run_batch(const std::vector<tn_net> &nets, const std::vector<DevPlan *> &pla
   }
   for (size_t q = n_persist; q < n; ++q) {
     const int rc = run_stepwise(nets[order[q]], plans[order[q]], nd[q], kp, st);
-    if (rc != TN_OK) {
-      (void)hipStreamSynchronize(st);      // copies from this call's host buffers may be pending
-      return rc;
-    }
+    if (rc != TN_OK) return rc;
   }
   HIP_TRY(hipEventRecord(ev.e1, st));
   HIP_TRY(hipEventSynchronize(ev.e1));
+  pending.done = true;
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
   *seconds = ms * 1e-3;
@@ -545,7 +551,9 @@ static int prepare_options(const tn_options *opt, tn_options &o, tn::KeepParams 
   if (!(o.tau_rel >= 0) || !(o.tau_deg >= 0)) return fail(TN_EINVAL, "tau_rel and tau_deg must be >= 0");
   for (int c = 0; c < 3; ++c)
     if (o.gemm_config[c] < 0 || o.gemm_config[c] > tn::kGemmConfigs) return fail(TN_EINVAL, "gemm_config out of range");
+  if (o.tridiag != TN_TRIDIAG_AUTO && o.tridiag != TN_TRIDIAG_QL) return fail(TN_EINVAL, "unknown tridiagonal solver");
   tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor * o.tau_rel};
+  kp.tridiag_ql = o.tridiag == TN_TRIDIAG_QL;
   kp.residual_tol = o.residual_tol;
   kp.split = o.precision == TN_FP64 ? 0 : (o.precision == TN_SPLIT_BF16X3 || o.precision == TN_SPLIT_BF16X3_ALL ? 1 : 2);
   kp.split_all = o.precision == TN_SPLIT_BF16X3_ALL || o.precision == TN_SPLIT_FP16X3_ALL ? 1 : 0;
@@ -1038,7 +1046,9 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, int32_t rest, const 
   op.flags |= tn::F_V_GLOBAL;
   std::vector<double> ws(lsz + usz + 2 * (np * np + np), 0.0);
   std::memcpy(ws.data(), L, size_t(n) * n * 8);
+  if (o.tridiag != TN_TRIDIAG_AUTO && o.tridiag != TN_TRIDIAG_QL) return fail(TN_EINVAL, "unknown tridiagonal solver");
   tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor * o.tau_rel};
+  kp.tridiag_ql = o.tridiag == TN_TRIDIAG_QL;
   if (o.eig == TN_EIG_LEARNED) {
     kp.model = o.model->d_w;
     kp.residual_tol = o.residual_tol;

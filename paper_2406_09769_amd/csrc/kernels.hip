@@ -923,7 +923,407 @@ __device__ void tri_reduce_wave(const EigWs &E) {
   }
 }
 
-__device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
+// ---------------------------------------------------------------- divide and conquer
+//
+// Tridiagonal eigensolve by divide and conquer for orders up to kDcMax, used in place of
+// QL where its work area fits LDS. Every off-diagonal e_i tears T into
+// diag(T1, T2) + rho v v^T (rho = |e_i|, v = e_i + sign(e_i) e_{i+1}), so the leaves are
+// the 1 x 1 blocks d_i - |e_{i-1}| - |e_i|; blocks are merged bottom-up, pairs of width
+// S/2 into width S. A merge of children with eigenpairs (D1, Q1), (D2, Q2) solves
+// D + rho z z^T with z = (last row of Q1, sign * first row of Q2):
+//  * deflation: components with rho |z_i| <= tol keep (D_i, column i); pairs of close
+//    D (|(D_j - D_i) c s| <= tol after the rotation that moves z_i into z_j) are rotated
+//    and one of them deflates; tol = 8 eps max(|D|, rho |z|) of the merge;
+//  * each remaining root lam_t of 1 + rho sum z_i^2 / (delta_i - lam) (delta ascending,
+//    one root in each (delta_t, delta_t+1), the last below delta_K + rho ||z||^2) is found
+//    by a group of lanes, as lam = delta_o + tau with the origin o the nearer pole, so that
+//    every delta_i - lam_t is formed without cancellation (dc_root);
+//  * the eigenvectors come from z recomputed from the roots (the Loewner formula of Gu
+//    and Eisenstat), which keeps them orthogonal to working accuracy:
+//    zh_i^2 = prod_t (lam_t - delta_i) / (rho prod_{t != i} (delta_t - delta_i)),
+//    u_t = (zh_i / (delta_i - lam_t))_i normalised;
+//  * the merged eigenvectors are Q u_t (kept) and the deflated columns of Q.
+// Eigenvector blocks alternate between two n x n buffers whose entries outside the
+// current blocks stay zero.
+constexpr int kDcMax = 64;
+__host__ __device__ constexpr int dc_lds_doubles(int n) { return n * n + n * (n + 1) + 16 * n; }
+
+struct DcWs {
+  double *Zb, *W;                                  // second eigenvector buffer; merge matrices
+  double *D, *z, *dk, *zk, *tau, *zh, *rc, *rs;    // per index (n each)
+  int *perm, *kept, *defl, *org, *rj, *ri, *cnt;   // per index; cnt: K, deflated, rotations at lo
+};
+
+__device__ DcWs dc_ws(double *base, int n) {
+  DcWs W;
+  W.Zb = base;
+  W.W = base + n * n;                              // n x (n + 1): odd pitch
+  double *v = W.W + n * (n + 1);
+  W.D = v; W.z = v + n; W.dk = v + 2 * n; W.zk = v + 3 * n; W.tau = v + 4 * n; W.zh = v + 5 * n;
+  W.rc = v + 6 * n; W.rs = v + 7 * n;
+  int *iv = reinterpret_cast<int *>(v + 8 * n);
+  W.perm = iv; W.kept = iv + n; W.defl = iv + 2 * n; W.org = iv + 3 * n; W.rj = iv + 4 * n;
+  W.ri = iv + 5 * n; W.cnt = iv + 6 * n;             // 3 ints per block start: up to 3n, in 8n doubles' room
+  return W;
+}
+
+// max over aligned groups of g lanes (g a power of two <= 64)
+__device__ __forceinline__ double group_max(double v, int g) {
+  for (int off = 1; off < g; off <<= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// sum and product over aligned groups of L lanes, L in {4, 8, 16} (all lanes of a group
+// active); every lane of the group gets the same value
+__device__ __forceinline__ double lsum(double v, int L) {
+  v = quad_sum(v);
+  if (L >= 8) v += dpp_f64<kDppRowHalfMirror>(v);
+  if (L >= 16) v += dpp_f64<kDppRowMirror>(v);
+  return v;
+}
+__device__ __forceinline__ double lprod(double v, int L) {
+  v *= dpp_f64<kDppQuadXor1>(v);
+  v *= dpp_f64<kDppQuadXor2>(v);
+  if (L >= 8) v *= dpp_f64<kDppRowHalfMirror>(v);
+  if (L >= 16) v *= dpp_f64<kDppRowMirror>(v);
+  return v;
+}
+
+// 1/x from the hardware estimate and two Newton steps (within an ulp or two for normal x)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Root in (lo, hi) of c + wl / (al - x) + wr / (ar - x) = 0, or lo - 1 if it has none there.
+__device__ double dc_quad_root(double c, double al, double ar, double wl, double wr, double lo, double hi) {
+  const double b = -(c * (al + ar) + wl + wr), cc = c * al * ar + wl * ar + wr * al;
+  if (c != 0.0) {
+    const double disc = b * b - 4.0 * c * cc;
+    if (disc < 0.0) return lo - 1.0;
+    const double q = -0.5 * (b + copysign(sqrt(disc), b));
+    const double x1 = q * rcp_nr(c);
+    if (lo < x1 && x1 < hi) return x1;
+    if (q != 0.0) {
+      const double x2 = cc * rcp_nr(q);
+      if (lo < x2 && x2 < hi) return x2;
+    }
+    return lo - 1.0;
+  }
+  if (b != 0.0) {
+    const double x = -cc * rcp_nr(b);
+    if (lo < x && x < hi) return x;
+  }
+  return lo - 1.0;
+}
+
+// Root t of 1 + rho sum_i z_i^2 / (delta_i - lam), i < K (delta ascending, rho > 0), by an
+// aligned group of L lanes (each sums every L-th term; all of them agree bit for bit). Returns tau with
+// lam = delta_o + tau, o in {t, t+1} the nearer pole. The start solves the model with the
+// two nearest poles at their exact weights and the others a constant; each step solves the
+// model with one pole on each side of the root, weighted to match the derivatives of the
+// two partial sums (for the last root: its own pole exact, the others at delta_{K-2}),
+// inside a bracket kept by the sign of f.
+__device__ double dc_root(const double *dk, const double *zk, int K, int t, double rho, int sub, int L,
+                        int *o_out) {
+  constexpr double kEps = 2.220446049250313e-16;
+  if (K == 1) { *o_out = 0; return rho * zk[0] * zk[0]; }
+  const double dt = dk[t];
+  int o, pa;
+  double lo, hi, tau, rest;
+  if (t < K - 1) {
+    const double mid = 0.5 * (dk[t + 1] - dt);
+    double f = 0.0, two = 0.0;
+    for (int i = sub; i < K; i += L) {
+      const double term = zk[i] * zk[i] * rcp_nr((dk[i] - dt) - mid);
+      f += term;
+      two += (i == t || i == t + 1) ? term : 0.0;
+    }
+    f = lsum(f, L);
+    two = lsum(two, L);
+    rest = f - two;
+    if (1.0 + rho * f >= 0.0) { o = t; lo = 0.0; hi = mid; tau = mid; }
+    else { o = t + 1; lo = -mid; hi = 0.0; tau = -mid; }
+    pa = t;
+  } else {
+    double s2 = 0.0, r = 0.0;
+    for (int i = sub; i < K; i += L) {
+      const double z2 = zk[i] * zk[i];
+      s2 += z2;
+      r += i + 2 < K ? z2 * rcp_nr(dk[i] - dt) : 0.0;   // the others seen from the origin
+    }
+    s2 = lsum(s2, L);
+    rest = lsum(r, L);
+    o = K - 1; lo = 0.0; hi = rho * s2; tau = 0.5 * hi;
+    pa = K - 2;
+  }
+  const double dko = dk[o];
+  const double pl = dk[pa] - dko, pr = dk[pa + 1] - dko;   // the two nearest poles
+  {
+    const double x = dc_quad_root(1.0 + rho * rest, pl, pr, rho * zk[pa] * zk[pa], rho * zk[pa + 1] * zk[pa + 1],
+                                  lo, hi);
+    if (x >= lo) tau = x;
+  }
+  const bool last = t == K - 1;
+  const double zo2 = zk[o] * zk[o];
+  for (int it = 0; it < 64; ++it) {
+    double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
+    for (int i = sub; i < K; i += L) {
+      const double w = zk[i] * rcp_nr((dk[i] - dko) - tau);
+      const double a = zk[i] * w, b = w * w;
+      const bool left = i <= t;
+      psi += left ? a : 0.0; dpsi += left ? b : 0.0;
+      phi += left ? 0.0 : a; dphi += left ? 0.0 : b;
+    }
+    psi = lsum(psi, L); phi = lsum(phi, L); dpsi = lsum(dpsi, L); dphi = lsum(dphi, L);
+    const double f = 1.0 + rho * (psi + phi);
+    const double err = kEps * (2.0 + 8.0 * rho * (phi - psi) + 3.0 * rho * fabs(tau) * (dpsi + dphi));   // psi < 0 < phi
+    if (f > 0.0) hi = tau;
+    else if (f < 0.0) lo = tau;
+    if (fabs(f) <= err || hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi))) break;
+    const double al = pl - tau, ar = pr - tau;
+    double sl, sr;
+    if (!last) { sl = dpsi * al * al; sr = dphi * ar * ar; }
+    else { sr = zo2; sl = (dpsi - zo2 * rcp_nr(ar * ar)) * al * al; }
+    const double c = f - rho * (sl * rcp_nr(al) + sr * rcp_nr(ar));
+    const double eta = dc_quad_root(c, al, ar, rho * sl, rho * sr, lo - tau, hi - tau);
+    const double nt = tau + eta;
+    if (eta >= lo - tau && lo < nt && nt < hi) {
+      if (nt == tau) break;                         // the step no longer moves tau
+      tau = nt;
+    } else {
+      tau = 0.5 * (lo + hi);
+    }
+  }
+  *o_out = o;
+  return tau;
+}
+
+// Wave 0, lane groups of width S (one merge each, blocks [lo, lo + S)): gather D and z,
+// order D, deflate, rotate the columns of Z the deflation pairs, and list the poles (dk, zk)
+// of the remaining secular equation. cnt[3lo] = K roots, cnt[3lo+1] deflated columns.
+// tol = 8 eps max(|D|, rho |z|) of the merge: each deflation perturbs the merged block by
+// at most that (a tolerance from ||T|| instead would perturb the small eigenvalues of a
+// graded matrix far more than a QL solve does).
+__device__ void dc_deflate(double *Z, const double *dd, const double *ee, const DcWs &W, int n, int S) {
+  constexpr double kEps = 2.220446049250313e-16;
+  const int lane = threadIdx.x & 63, g = S < 64 ? S : 64;
+  const int base = (lane / g) * g, lo = (lane / g) * S, t = lane - base;
+  const int m = lo + S / 2, hi = lo + S < n ? lo + S : n;
+  const bool merge = lo < n && m < hi;
+  const int s = merge ? hi - lo : 0, n1 = m - lo;
+  const bool act = t < s;
+  double rho = 0.0, Dt = 0.0, zt = 0.0;
+  if (merge) {
+    const double e = ee[m - 1];
+    rho = 2.0 * fabs(e);
+    if (act) {                                      // z: last row of Q1, first row of Q2
+      Dt = dd[lo + t];
+      zt = (t < n1 ? Z[(lo + t) * n + (m - 1)] : copysign(1.0, e) * Z[(lo + t) * n + m]) * 0.70710678118654752440;
+      W.D[lo + t] = Dt;
+      W.z[lo + t] = zt;
+    }
+  }
+  __threadfence_block();
+  if (act) {                                        // ascending order, ties by index
+    int r = 0;
+    for (int u = 0; u < s; ++u) {
+      const double du = W.D[lo + u];
+      r += (du < Dt) || (du == Dt && u < t);
+    }
+    W.perm[lo + r] = t;
+  }
+  const double dmax = group_max(act ? fabs(Dt) : 0.0, g), zmax = group_max(act ? fabs(zt) : 0.0, g);
+  const double tol = 8.0 * kEps * fmax(dmax, rho * zmax);
+  __threadfence_block();
+  // lane = sorted position: small rho |z| deflates; when no neighbouring pair of the others
+  // is close enough to rotate, the others are the poles in order
+  const int ip = act ? W.perm[lo + t] : 0;
+  const double Dp = act ? W.D[lo + ip] : 0.0, zp = act ? W.z[lo + ip] : 0.0;
+  const bool big = act && rho > 0.0 && rho * fabs(zp) > tol;
+  const unsigned long long gmask = (g == 64 ? ~0ull : ((1ull << g) - 1)) << base;
+  const unsigned long long below = (1ull << lane) - 1;
+  const unsigned long long nsm = __ballot(big) & gmask;
+  const unsigned long long after = nsm & ~below & ~(1ull << lane);
+  const int nx = after ? __ffsll((long long)after) - 1 : lane;
+  const double Dn = __shfl(Dp, nx, 64), zn = __shfl(zp, nx, 64);
+  bool close = false;
+  if (big && after) {
+    const double tt = hypot(zp, zn);
+    close = fabs((Dn - Dp) * (zn / tt) * (zp / tt)) <= tol;
+  }
+  const unsigned long long closem = __ballot(close) & gmask;
+  if (!closem) {
+    if (act) {
+      if (big) W.kept[lo + __popcll(nsm & below)] = ip;
+      else W.defl[lo + __popcll(~nsm & gmask & below)] = ip;
+    }
+    if (merge && t == 0) {
+      const int K = __popcll(nsm);
+      W.cnt[3 * lo] = K; W.cnt[3 * lo + 1] = s - K; W.cnt[3 * lo + 2] = 0;
+    }
+  } else if (merge && t == 0) {                     // rotations needed: one lane per merge
+    int K = 0, nd = 0, nr = 0, cand = -1;
+    for (int p = 0; p < s; ++p) {
+      const int i = W.perm[lo + p];
+      const double zi = W.z[lo + i];
+      if (rho * fabs(zi) <= tol) { W.defl[lo + nd++] = i; continue; }
+      if (cand < 0) { cand = i; continue; }
+      const double zc = W.z[lo + cand];
+      const double tt = hypot(zc, zi), c = zi / tt, sn = -zc / tt;
+      const double dc = W.D[lo + cand], di = W.D[lo + i];
+      if (fabs((di - dc) * c * sn) <= tol) {
+        W.rj[lo + nr] = cand; W.ri[lo + nr] = i; W.rc[lo + nr] = c; W.rs[lo + nr] = sn; ++nr;
+        W.D[lo + cand] = dc * c * c + di * sn * sn;
+        W.D[lo + i] = dc * sn * sn + di * c * c;
+        W.z[lo + i] = tt;
+        W.z[lo + cand] = 0.0;
+        W.defl[lo + nd++] = cand;
+      } else {
+        W.kept[lo + K++] = cand;
+      }
+      cand = i;
+    }
+    if (cand >= 0) W.kept[lo + K++] = cand;
+    W.cnt[3 * lo] = K; W.cnt[3 * lo + 1] = nd; W.cnt[3 * lo + 2] = nr;
+  }
+  __threadfence_block();
+  const int K = merge ? W.cnt[3 * lo] : 0, nr = merge ? W.cnt[3 * lo + 2] : 0;
+  if (act) {                                        // deflation rotations on row lo+t of Q
+    const int row = lo + t;
+    for (int r = 0; r < nr; ++r) {
+      double *qa = Z + (lo + W.rj[lo + r]) * n + row, *qb = Z + (lo + W.ri[lo + r]) * n + row;
+      const double c = W.rc[lo + r], sn = W.rs[lo + r], x = *qa, y = *qb;
+      *qa = c * x + sn * y;
+      *qb = -sn * x + c * y;
+    }
+  }
+  if (t < K) { W.dk[lo + t] = W.D[lo + W.kept[lo + t]]; W.zk[lo + t] = W.z[lo + W.kept[lo + t]]; }
+}
+
+// The merge and the position within it that quad q (= index q of the level) stands for.
+struct DcPos {
+  int lo, t, s, K;
+  bool merge;
+};
+__device__ __forceinline__ DcPos dc_pos(const DcWs &W, int n, int S, int q) {
+  DcPos P;
+  P.lo = (q / S) * S;
+  P.t = q - P.lo;
+  const int hi = P.lo + S < n ? P.lo + S : n;
+  P.merge = P.lo < n && P.lo + S / 2 < hi;
+  P.s = P.merge ? hi - P.lo : 0;
+  P.K = P.merge ? W.cnt[3 * P.lo] : 0;
+  return P;
+}
+
+// Eigenpairs of the tridiagonal (E.dd, E.ee) by divide and conquer: eigenvalues in E.dd
+// (unordered), eigenvectors in E.A as Z (column j at E.A[j n ..]), as the QL solve leaves them.
+// Per level: wave 0 deflates every merge; then groups of L lanes (one per index of the
+// level) find the roots and write delta_i - lam_t (column t of the merge's block of W, odd
+// pitch pw), recompute z, form and normalise the vectors u_t; then the workgroup multiplies.
+__device__ void tri_dc(const EigWs &E, double *base) {
+  const int n = E.n, tid = threadIdx.x, wave = tid >> 6;
+  const int L = n <= 16 ? 16 : (n <= 32 ? 8 : 4);  // lanes per index of a level
+  const int q = tid / L, sub = tid % L;
+  const DcWs W = dc_ws(base, n);
+  const int pw = n + 1;
+  double *Za = E.A, *Zb = W.Zb;
+  for (int e = tid; e < n * n; e += kThreads) {
+    Za[e] = (e / n == e % n) ? 1.0 : 0.0;
+    Zb[e] = 0.0;
+  }
+  for (int i = tid; i < n; i += kThreads)           // the tears: leaves d_i - |e_i-1| - |e_i|
+    E.dd[i] -= (i > 0 ? fabs(E.ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(E.ee[i]) : 0.0);
+  __syncthreads();
+  double *Zc = Za, *Zn = Zb;
+  for (int S = 2; S / 2 < n; S *= 2) {
+    if (wave == 0) dc_deflate(Zc, E.dd, E.ee, W, n, S);
+    __syncthreads();
+    const DcPos P = dc_pos(W, n, S, q);
+    const double *dk = W.dk + P.lo, *zk = W.zk + P.lo;
+    double *U = W.W + P.lo * pw + P.lo;             // (delta_i - lam_t), then u: U[t pw + i]
+    const double rho = P.merge ? 2.0 * fabs(E.ee[P.lo + S / 2 - 1]) : 0.0;
+    if (q < n && P.t < P.K) {                       // root t
+      int o;
+      const double tau = dc_root(dk, zk, P.K, P.t, rho, sub, L, &o);
+      const double dko = dk[o];
+      if (sub == 0) W.tau[P.lo + P.t] = dko + tau;
+      for (int i = sub; i < P.K; i += L) U[P.t * pw + i] = (dk[i] - dko) - tau;
+    }
+    __syncthreads();
+    if (q < n && P.t < P.K) {                       // zh_t from row t of (delta_i - lam)
+      const int t = P.t, K = P.K;
+      const double dt = dk[t];
+      double p = 1.0;
+      for (int u = sub; u < K; u += L) {
+        const double num = -U[u * pw + t];
+        p *= u == K - 1 ? num / rho : num * rcp_nr((u < t ? dk[u] : dk[u + 1]) - dt);
+      }
+      p = lprod(p, L);
+      if (sub == 0) W.zh[P.lo + t] = copysign(sqrt(p), zk[t]);
+    }
+    __syncthreads();
+    if (q < n && P.t < P.s) {                       // column t of u, normalised; the eigenvalues
+      const int t = P.t, K = P.K;
+      if (t < K) {
+        double nrm = 0.0;
+        for (int i = sub; i < K; i += L) {
+          const double u = W.zh[P.lo + i] * rcp_nr(U[t * pw + i]);
+          U[t * pw + i] = u;
+          nrm = fma(u, u, nrm);
+        }
+        const double sc = 1.0 / sqrt(lsum(nrm, L));
+        for (int i = sub; i < K; i += L) U[t * pw + i] *= sc;
+      }
+      if (sub == 0) E.dd[P.lo + t] = t < K ? W.tau[P.lo + t] : W.D[P.lo + W.defl[P.lo + (t - K)]];
+    }
+    __syncthreads();
+    // Zn's blocks: kept columns Q u_t, then the deflated columns of Q (or the block as it
+    // is where nothing merges); 4 columns per thread share each load of Q
+    const int nb = (n + S - 1) / S, per = S * ((S + 3) / 4);
+    for (int e = tid; e < nb * per; e += kThreads) {
+      const int blk = e / per, r = e % per;
+      const int lo = blk * S, hi = lo + S < n ? lo + S : n, s = hi - lo;
+      const int row = r % S, j0 = (r / S) * 4;
+      if (row >= s || j0 >= s) continue;
+      const bool merge = lo + S / 2 < hi;
+      const int K = merge ? W.cnt[3 * lo] : 0;
+      const int jn = j0 < K ? (K - j0 < 4 ? K - j0 : 4) : 0;       // product columns here
+      if (jn > 0) {
+        const double *Ub = W.W + lo * pw + lo;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int i = 0; i < K; ++i) {
+          const double qv = Zc[(lo + W.kept[lo + i]) * n + lo + row];
+          a0 = fma(qv, Ub[j0 * pw + i], a0);
+          if (jn > 1) a1 = fma(qv, Ub[(j0 + 1) * pw + i], a1);
+          if (jn > 2) a2 = fma(qv, Ub[(j0 + 2) * pw + i], a2);
+          if (jn > 3) a3 = fma(qv, Ub[(j0 + 3) * pw + i], a3);
+        }
+        double *out = Zn + (lo + j0) * n + lo + row;
+        out[0] = a0;
+        if (jn > 1) out[n] = a1;
+        if (jn > 2) out[2 * n] = a2;
+        if (jn > 3) out[3 * n] = a3;
+      }
+      for (int j = j0 + jn; j < j0 + 4 && j < s; ++j) {          // deflated (or unmerged) columns
+        const int src = merge ? lo + W.defl[lo + (j - K)] : lo + j;
+        Zn[(lo + j) * n + lo + row] = Zc[src * n + lo + row];
+      }
+    }
+    __syncthreads();
+    double *tmp = Zc; Zc = Zn; Zn = tmp;
+  }
+  if (Zc != Za) {
+    for (int e = tid; e < n * n; e += kThreads) Za[e] = Zc[e];
+    __syncthreads();
+  }
+}
+
+// Tridiagonalise E.A and solve T: by divide and conquer into the work area at dcws when
+// given (order <= kDcMax), else by implicit QL.
+__device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed, double *dcws = nullptr) {
   const int n = E.n, pa = E.pa, tid = threadIdx.x, wave = tid >> 6;
   double *A = E.A, *vv = E.vv, *pp = E.pp, *ww = E.ww, *dd = E.dd, *ee = E.ee, *hv = E.hv;
   long long tph = wall_clock64();
@@ -1019,6 +1419,11 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed) {
   }
   __syncthreads();
   if (timed && tid == 0) { const long long t = wall_clock64(); sc->ticks[0] += t - tph; tph = t; }
+  if (dcws) {
+    tri_dc(E, dcws);
+    if (timed && tid == 0) sc->ticks[6] += wall_clock64() - tph;
+    return;
+  }
 
   double *Z = A;
   for (int e = tid; e < n * n; e += kThreads) Z[e] = (e / n == e % n) ? 1.0 : 0.0;
@@ -1633,7 +2038,10 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
     E.A[i * E.pa + j] = 0.5 * (L[int64_t(i) * ld + j] + L[int64_t(j) * ld + i]);
   }
   __syncthreads();
-  tri_ql(E, sc, true);
+  // divide and conquer where its work area fits beside the solve's, else QL
+  double *dcws = lds + eig_lds_doubles(n) + (hv_lds ? n * n + n : 0);
+  const bool dc = !big && !kp.tridiag_ql && n <= kDcMax && dcws + dc_lds_doubles(n) <= lds + kLdsDoubles;
+  tri_ql(E, sc, true, dc ? dcws : nullptr);
   t0 = wall_clock64();
   order_desc(E);
   if (tid == 0) {

@@ -34,6 +34,8 @@ struct KeepParams {
                            // 1 = every GEMM
   int gemm_cfg[3];         // FP64 GEMM block configuration for ops of <= 16, <= 32, > 32 rows:
                            // 0 = built-in choice, k = candidate k-1 of kGemmConfigs
+  int tridiag_ql;          // 1: implicit QL for every tridiagonal solve; 0: divide and
+                           // conquer where it fits (orders up to 64)
 };
 
 // The FP64 pipelined GEMM's candidate block configurations (rows x columns per block,

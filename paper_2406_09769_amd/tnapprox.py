@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtnapprox.so")
 TN_OK, TN_EINVAL, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_EUNSUPPORTED = range(6)
 TN_FP64, TN_SPLIT_BF16X3, TN_SPLIT_FP16X3, TN_SPLIT_BF16X3_ALL, TN_SPLIT_FP16X3_ALL = range(5)
 TN_EIG_EXACT, TN_EIG_LEARNED = range(2)
+TN_TRIDIAG_AUTO, TN_TRIDIAG_QL = range(2)
 
 
 class TnError(RuntimeError):
@@ -47,7 +48,7 @@ class tn_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eig", C.c_int32), ("residual_tol", C.c_double),
                 ("tau_rel", C.c_double), ("tau_deg", C.c_double), ("hip_stream", C.c_void_p),
                 ("model", C.c_void_p), ("gemm_config", C.c_int32 * 3), ("chunks", C.c_int32),
-                ("progress", PROGRESS), ("progress_ctx", C.c_void_p)]
+                ("progress", PROGRESS), ("progress_ctx", C.c_void_p), ("tridiag", C.c_int32)]
 
 
 class tn_result(C.Structure):
@@ -155,13 +156,13 @@ _LIVE = []   # the progress callback of the call in flight (kept alive across it
 
 
 def _options(precision=TN_FP64, eig=TN_EIG_EXACT, residual_tol=1e-6, tau_rel=1e-12, tau_deg=0.1,
-             stream=None, model=None, gemm_config=(0, 0, 0), chunks=0, progress=None):
+             stream=None, model=None, gemm_config=(0, 0, 0), chunks=0, progress=None, tridiag=0):
     """progress: a Python callable (done, total) called after each part when chunks > 1."""
     cb = PROGRESS(lambda ctx, done, total: progress(int(done), int(total))) if progress else PROGRESS()
     _LIVE[:] = [cb]
     return tn_options(int(precision), int(eig), float(residual_tol), float(tau_rel), float(tau_deg),
                       C.c_void_p(stream) if stream else None, model.ptr if model is not None else None,
-                      (C.c_int32 * 3)(*[int(x) for x in gemm_config]), int(chunks), cb, None)
+                      (C.c_int32 * 3)(*[int(x) for x in gemm_config]), int(chunks), cb, None, int(tridiag))
 
 
 @dataclass
@@ -291,7 +292,7 @@ def tn_debug_gemm(A: np.ndarray, B: np.ndarray, lo_split: int = 1 << 30, precisi
 
 
 def tn_debug_eig(L: np.ndarray, ucols: int, tau_rel=1e-12, tau_deg=0.1, rest: int = 0, model=None,
-                 residual_tol=1e-6, stats: bool = False):
+                 residual_tol=1e-6, stats: bool = False, tridiag: int = 0):
     """Kept eigenvectors (n x ucols, zero past the kept rank) and the fallback flag;
     with stats=True also the dict of the learned warm start's outcome."""
     L = np.ascontiguousarray(L, dtype=np.float64)
@@ -299,7 +300,7 @@ def tn_debug_eig(L: np.ndarray, ucols: int, tau_rel=1e-12, tau_deg=0.1, rest: in
     U = np.zeros((n, ucols))
     st = (C.c_int64 * 8)()
     o = _options(tau_rel=tau_rel, tau_deg=tau_deg, residual_tol=residual_tol,
-                 eig=TN_EIG_LEARNED if model is not None else TN_EIG_EXACT, model=model)
+                 eig=TN_EIG_LEARNED if model is not None else TN_EIG_EXACT, model=model, tridiag=tridiag)
     _check(LIB.tn_debug_eig(_dptr(L), n, int(ucols), int(rest), C.byref(o), _dptr(U), st))
     if not stats:
         return U, int(st[0])

@@ -67,6 +67,48 @@ def test_eig_subspace_and_rank_match_oracle(T, n):
     assert np.max(np.abs(P @ L @ P - Po @ L @ Po)) < 10 * n * eps * wo[0]
 
 
+def _hard_spectra(n, rng):
+    """Spectra that stress a tridiagonal solver's deflation: geometric decay over 35
+    orders, exact triples, a rank-deficient matrix (zeros), one eigenvalue repeated n
+    times, and n eigenvalues within 1e-9 of each other."""
+    yield "geometric", np.sort(np.exp(-rng.uniform(0, 35, n)))[::-1]
+    yield "triples", np.repeat(np.exp(-2.0 * np.arange((n + 2) // 3)), 3)[:n]
+    w = np.zeros(n)
+    r = max(1, n // 4)
+    w[:r] = np.sort(np.exp(-rng.uniform(0, 5, r)))[::-1]
+    yield "rank_deficient", w
+    yield "flat", np.ones(n)
+    yield "near_flat", np.sort(1.0 + 1e-9 * rng.standard_normal(n))[::-1]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16, 24, 32, 40, 47, 56, 63, 64])
+def test_eig_divide_and_conquer_matches_ql_and_oracle(T, n):
+    """The divide-and-conquer tridiagonal solve (orders up to 64) against the QL solve and
+    the oracle: same kept rank, orthonormal vectors, and kept subspaces that agree within
+    eps ||L|| / gap at the cut (both solvers are backward stable)."""
+    rng = np.random.default_rng(100 + n)
+    eps = np.finfo(float).eps
+    for name, w in _hard_spectra(n, rng):
+        L = _psd(n, w, n + 7)
+        ucols = max(1, n // 2)
+        Ud, fbd = T.tn_debug_eig(L, ucols, tridiag=T.TN_TRIDIAG_AUTO)
+        Uq, fbq = T.tn_debug_eig(L, ucols, tridiag=T.TN_TRIDIAG_QL)
+        Uo, wo, k, fbo = dm.keep(L, ucols)
+        kd = int(np.sum(np.any(Ud != 0.0, axis=0)))
+        kq = int(np.sum(np.any(Uq != 0.0, axis=0)))
+        assert (kd, fbd) == (kq, fbq) == (k, int(fbo)), (name, kd, kq, k)
+        Uk = Ud[:, :k]
+        assert np.allclose(Uk.T @ Uk, np.eye(k), atol=1e-12), name
+        if fbo:                      # nothing separates: any orthonormal choice is valid
+            continue
+        gap = wo[k - 1] - (wo[k] if k < n else 0.0)
+        P, Pq, Po = Uk @ Uk.T, Uq[:, :k] @ Uq[:, :k].T, Uo @ Uo.T
+        bound = max(1e-9, 8 * n * eps * wo[0] / gap)
+        assert np.max(np.abs(P - Po)) < bound, (name, np.max(np.abs(P - Po)), bound)
+        assert np.max(np.abs(P - Pq)) < bound, (name, np.max(np.abs(P - Pq)), bound)
+        assert np.max(np.abs(P @ L @ P - Po @ L @ Po)) < 10 * n * eps * wo[0], name
+
+
 def test_eig_does_not_split_degenerate_cluster(T):
     w = np.array([1.0, 0.5, 0.25, 0.25, 0.1, 0.0])
     L = _psd(6, w, 3)
