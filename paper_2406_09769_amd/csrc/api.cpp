@@ -39,6 +39,10 @@ struct Seg {
   bool piped;        // kind 1: offsets fit the pipelined chip-wide kernel
   int64_t split_bytes = 0;   // kind 1: scratch of the split forms' operand planes
   int split_blocks = 0;      // kind 1: workgroups of the split forms' operand pass
+  int kchunks = 1;           // kind 1, FP64 tiled: parts of K (split K), scratch kpart doubles
+  int64_t kpart = 0;
+  int stream_k = 0;          // kind 1, FP64: streamed (K class), over stream_blocks workgroups
+  int stream_blocks = 0;
 };
 
 struct DevPlan {
@@ -101,6 +105,8 @@ struct tn_net_s {
   double *d_part = nullptr;
   unsigned short *d_split = nullptr;   // split forms: operand planes of the chip-wide GEMMs
   int64_t split_cap = 0;
+  double *d_kpart = nullptr;           // split-K partial products of the chip-wide GEMMs
+  int64_t kpart_cap = 0;
   hipStream_t cap_stream = nullptr;
   ~tn_net_s() {
     plans.clear();
@@ -108,6 +114,7 @@ struct tn_net_s {
     if (d_nd) (void)hipFree(d_nd);
     if (d_part) (void)hipFree(d_part);
     if (d_split) (void)hipFree(d_split);
+    if (d_kpart) (void)hipFree(d_kpart);
     if (d_const) (void)hipFree(d_const);
     if (d_ws) (void)hipFree(d_ws);
     if (d_sc) (void)hipFree(d_sc);
@@ -176,8 +183,15 @@ void make_segments(DevPlan &dp) {
     if (kind) {
       segs.push_back(Seg{kind, i, i + 1, std::max(blocks, 1), piped});
       if (kind == 1) {
-        segs.back().split_bytes = tn::split_scratch_bytes(op.am.n, op.bn.n, op.K);
-        segs.back().split_blocks = tn::split_grid_blocks(op.am.n, op.bn.n, op.K);
+        Seg &sg = segs.back();
+        sg.split_bytes = tn::split_scratch_bytes(op.am.n, op.bn.n, op.K);
+        sg.split_blocks = tn::split_grid_blocks(op.am.n, op.bn.n, op.K);
+        if (!piped) {
+          sg.kchunks = tn::grid_kchunks(op.am.n, op.bn.n, op.K);
+          sg.kpart = tn::grid_kpart_doubles(op.am.n, op.bn.n, op.K);
+        }
+        sg.stream_k = tn::stream_kclass(op.am.n, op.bn.n, op.K);
+        sg.stream_blocks = tn::stream_blocks(op.bn.n);
       }
     } else if (!segs.empty() && segs.back().kind == 0) {
       segs.back().last = i + 1;
@@ -304,10 +318,17 @@ thread_local std::map<int, BatchCtx> g_batch;
 int launch_segments(tn_net net, DevPlan *dp, const tn::KeepParams &kp, hipStream_t st) {
   for (const Seg &sg : dp->segs) {
     if (sg.kind == 0) HIP_TRY(tn::launch_interp_range(net->d_nd, sg.first, sg.last, kp, st));
-    else if (sg.kind == 1)
-      HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, sg.blocks, tn::op_split(kp, dp->plan.ops[size_t(sg.first)].flags),
-                                   sg.piped, net->d_split, sg.split_blocks, st));
-    else HIP_TRY(tn::launch_rescale_grid(net->d_nd, sg.first, sg.blocks, net->d_part, st));
+    else if (sg.kind == 1) {
+      const int sp = tn::op_split(kp, dp->plan.ops[size_t(sg.first)].flags);
+      const int sk = sp ? 0 : sg.stream_k;          // FP64 only: streamed, else split K (tiled path)
+      const int kc = sp || sk ? 1 : sg.kchunks;
+      const int blocks = sk ? sg.stream_blocks
+                            : (kc > 1 ? int(std::min<int64_t>(tn::kGridBlocks, int64_t(sg.blocks) * kc)) : sg.blocks);
+      HIP_TRY(tn::launch_gemm_grid(net->d_nd, sg.first, blocks, sp, sg.piped, net->d_split, sg.split_blocks, kc,
+                                   net->d_kpart, sk, st));
+    } else {
+      HIP_TRY(tn::launch_rescale_grid(net->d_nd, sg.first, sg.blocks, net->d_part, st));
+    }
   }
   return TN_OK;
 }
@@ -334,9 +355,24 @@ int run_stepwise(tn_net net, DevPlan *dp, const tn::NetDev &nd, const tn::KeepPa
       net->split_cap = need;
     }
   }
+  {                                         // split-K partial products of the plan's FP64 tiled GEMMs
+    int64_t need = 0;
+    for (const Seg &sg : dp->segs)
+      if (sg.kind == 1 && !tn::op_split(kp, dp->plan.ops[size_t(sg.first)].flags)) need = std::max(need, sg.kpart);
+    if (need > net->kpart_cap) {
+      HIP_TRY(hipStreamSynchronize(st));    // earlier launches may still use the old buffer
+      if (net->d_kpart) (void)hipFree(net->d_kpart);
+      net->d_kpart = nullptr;
+      net->kpart_cap = 0;
+      if (hipMalloc(&net->d_kpart, size_t(need) * sizeof(double)) != hipSuccess)
+        return fail(TN_ENOMEM, "split-K scratch allocation of " + std::to_string(need * 8) + " bytes failed");
+      net->kpart_cap = need;
+    }
+  }
   HIP_TRY(hipMemcpyAsync(net->d_nd, &nd, sizeof(nd), hipMemcpyHostToDevice, st));
   std::vector<char> key = kp_key(kp);
   key_put(key, &net->d_split, sizeof(net->d_split));
+  key_put(key, &net->d_kpart, sizeof(net->d_kpart));
   auto it = dp->gexecs.find(key);
   if (it == dp->gexecs.end()) {
     if (dp->gexecs.size() >= kMaxGraphsPerPlan) {   // bounded cache: earlier launches have completed
@@ -909,7 +945,8 @@ int tn_profile_last(tn_net net, double *seconds_by_kind) {
 // slots: the kept-rank slots (in: initial extents, default 1; out: as left by the ops).
 static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t> &tab, std::vector<double> &ws,
                       const std::vector<double> &cst, const tn::KeepParams &kp, tn::NetScalars *sc_out,
-                      std::vector<int32_t> *slots_io = nullptr, int grid_blocks = 0, bool grid_piped = false) {
+                      std::vector<int32_t> *slots_io = nullptr, int grid_blocks = 0, bool grid_piped = false,
+                      int grid_kchunks = 1, int grid_stream_k = 0) {
   int rc = check_device();
   if (rc != TN_OK) return rc;
   tn::Op *d_ops = nullptr;
@@ -918,9 +955,10 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
   tn::NetScalars *d_sc = nullptr;
   tn::NetDev *d_nd = nullptr;
   unsigned short *d_planes = nullptr;
+  double *d_kpart = nullptr;
   auto cleanup = [&]() {
     (void)hipFree(d_ops); (void)hipFree(d_tab); (void)hipFree(d_ws); (void)hipFree(d_cst);
-    (void)hipFree(d_sc); (void)hipFree(d_nd); (void)hipFree(d_planes);
+    (void)hipFree(d_sc); (void)hipFree(d_nd); (void)hipFree(d_planes); (void)hipFree(d_kpart);
   };
   if (hipMalloc(&d_ops, ops.size() * sizeof(tn::Op)) != hipSuccess ||
       hipMalloc(&d_tab, std::max<size_t>(tab.size(), 1) * 4) != hipSuccess ||
@@ -951,9 +989,15 @@ static int run_single(const std::vector<tn::Op> &ops, const std::vector<int32_t>
     split_blocks = tn::split_grid_blocks(op.am.n, op.bn.n, op.K);
     e = hipMalloc(&d_planes, size_t(tn::split_scratch_bytes(op.am.n, op.bn.n, op.K)));
   }
+  const int kc = grid_blocks > 0 && !kp.split && !grid_piped && !grid_stream_k ? grid_kchunks : 1;
+  if (e == hipSuccess && kc > 1) {
+    const tn::Op &op = ops[0];
+    e = hipMalloc(&d_kpart, size_t(kc) * op.am.n * op.bn.n * sizeof(double));
+  }
   if (e == hipSuccess)   // one op over the whole chip, else the interpreter's single workgroup
-    e = grid_blocks > 0 ? tn::launch_gemm_grid(d_nd, 0, grid_blocks, kp.split, grid_piped, d_planes, split_blocks,
-                                               nullptr)
+    e = grid_blocks > 0 ? tn::launch_gemm_grid(d_nd, 0, kc > 1 ? std::min(tn::kGridBlocks, grid_blocks * kc) : grid_blocks,
+                                               kp.split, grid_piped, d_planes, split_blocks, kc, d_kpart,
+                                               grid_stream_k, nullptr)
                         : tn::launch_interp(d_nd, 1, kp, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess && !ws.empty()) e = hipMemcpy(ws.data(), d_ws + 32, ws.size() * 8, hipMemcpyDeviceToHost);
@@ -1010,13 +1054,16 @@ int tn_debug_gemm(const double *A, int64_t sam, int64_t sak, const double *B, in
   if (precision < TN_FP64 || precision > TN_SPLIT_FP16X3_ALL) return fail(TN_EINVAL, "unknown precision");
   kp.split = precision == TN_FP64 ? 0 : (precision == TN_SPLIT_BF16X3 || precision == TN_SPLIT_BF16X3_ALL ? 1 : 2);
   kp.split_all = 1;                 // the diagnostic product is split whatever its class
-  int blocks = 0;
+  int blocks = 0, kchunks = 1, stream_k = 0;
   bool piped = false;
   if (chip_wide) {   // the launch the planner gives a chip-wide contraction of this shape
     blocks = int(std::min<int64_t>(tn::kGridBlocks, ((int64_t(M) + 63) / 64) * ((int64_t(N) + 63) / 64)));
     piped = int64_t(M) + K <= int64_t(tn::kGridOffsetDoubles) && int64_t(M) * N < (int64_t(1) << 31);
+    if (!piped) kchunks = tn::grid_kchunks(M, N, K);
+    if (!kp.split) stream_k = tn::stream_kclass(M, N, K);
+    if (stream_k) blocks = tn::stream_blocks(N);
   }
-  int rc = run_single({op}, tab, ws, cst, kp, nullptr, nullptr, blocks, piped);
+  int rc = run_single({op}, tab, ws, cst, kp, nullptr, nullptr, blocks, piped, kchunks, stream_k);
   if (rc != TN_OK) return rc;
   std::memcpy(C, ws.data(), ws.size() * 8);
   return TN_OK;

@@ -72,10 +72,14 @@ constexpr int kKCache = 4096;          // k offsets cached in LDS when K <= kKCa
 // slices): the fallback for ops whose offsets do not fit the pipelined path's caches.
 // The k offsets of both operands are cached in LDS when K <= KCACHE (lds holds two
 // k-slices, then 2 KCACHE int32). Kept out of line, as one body per cache size.
+// With kchunks > 1 (split K, chip-wide only) the work items are (tile, part of K): item w
+// takes tile w / kchunks over the kchunks-th share of K and writes its partial tile to
+// kpart[(part M + row) N + col] instead of C.
 template <int KCACHE>
 __device__ __noinline__ void gemm_tiles_k(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
                                           double *__restrict__ C, const int32_t *__restrict__ tab, double *lds,
-                                          int t_begin, int t_step, NetScalars *sc) {
+                                          int t_begin, int t_step, NetScalars *sc, int kchunks = 1,
+                                          double *__restrict__ kpart = nullptr) {
   // runtime extents; the output keeps its static row length
   const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
   const int NS = op.bn.n;
@@ -100,7 +104,10 @@ __device__ __noinline__ void gemm_tiles_k(const Op &op, const double *__restrict
     __syncthreads();
   }
 
-  for (int tile = t_begin; tile < ntiles; tile += t_step) {
+  const int kc_len = ((K + kchunks - 1) / kchunks + kTK - 1) / kTK * kTK;   // K per part, whole slices
+  for (int w = t_begin; w < ntiles * kchunks; w += t_step) {
+    const int tile = w / kchunks, part = w - tile * kchunks;
+    const int k_lo = part * kc_len, k_hi = k_lo + kc_len < K ? k_lo + kc_len : K;
     const int m0 = (tile / tilesN) * kTile, n0 = (tile % tilesN) * kTile;
     int64_t aoff[4], boff[4];
     int ai[4], ak_[4], bi[4], bk_[4];
@@ -125,11 +132,11 @@ __device__ __noinline__ void gemm_tiles_k(const Op &op, const double *__restrict
       for (int q = 0; q < 4; ++q) {
         const int k = k0 + ak_[q];
         double x = 0.0;
-        if (av[q] && k < K) x = A[aoff[q] + (kcached ? kA[k] : tab[op.ak + box_conv(op.bk_, k)])];
+        if (av[q] && k < k_hi) x = A[aoff[q] + (kcached ? kA[k] : tab[op.ak + box_conv(op.bk_, k)])];
         va[q] = x;
         const int kb = k0 + bk_[q];
         double y = 0.0;
-        if (bv[q] && kb < K) y = B[boff[q] + (kcached ? kB[kb] : tab[op.bk + box_conv(op.bk_, kb)])];
+        if (bv[q] && kb < k_hi) y = B[boff[q] + (kcached ? kB[kb] : tab[op.bk + box_conv(op.bk_, kb)])];
         vb[q] = y;
       }
     };
@@ -139,15 +146,15 @@ __device__ __noinline__ void gemm_tiles_k(const Op &op, const double *__restrict
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    load(0);
-    for (int k0 = 0; k0 < K; k0 += kTK) {
+    load(k_lo);
+    for (int k0 = k_lo; k0 < k_hi; k0 += kTK) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         As[ak_[q] * kPitch + ai[q]] = va[q];
         Bs[bk_[q] * kPitch + bi[q]] = vb[q];
       }
       __syncthreads();
-      if (k0 + kTK < K) load(k0 + kTK);   // next slice in flight during the MFMAs
+      if (k0 + kTK < k_hi) load(k0 + kTK);   // next slice in flight during the MFMAs
 #pragma unroll
       for (int kk = 0; kk < kTK; kk += 4) {
         const int kr = kk + (lane >> 4);
@@ -170,8 +177,10 @@ __device__ __noinline__ void gemm_tiles_k(const Op &op, const double *__restrict
         for (int r = 0; r < 4; ++r) {
           const int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;   // D: lane l, reg r = row l/16 + 4r
           const int col = n0 + wn * 32 + j * 16 + (lane & 15);
-          if (row < M && col < N)
-            C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = acc[i][j][r];
+          if (row < M && col < N) {
+            if (kpart) kpart[(int64_t(part) * M + row) * N + col] = acc[i][j][r];
+            else C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = acc[i][j][r];
+          }
         }
   }
 }
@@ -739,7 +748,8 @@ struct EigWs {          // LDS work area of one solve of order n
   double *gw;           // 24: Gram matrix and betas of a reflector block
   double *hv;           // reflectors: v_j at hv[j*n + i], beta_j at hv[n*n + j] (LDS past the
                         // work area when they fit, else the op's global scratch)
-  int n, pa;
+  int n, pa;            // pa: odd row pitch of the matrix, and the column pitch of Z (column j
+                        // at A[j pa ..]: lanes reading different columns hit different banks)
 };
 
 __host__ __device__ constexpr int eig_lds_doubles(int n) { return n * (n + 1) + 14 * n + (n + 1) / 2 + 8 + 24; }
@@ -772,7 +782,7 @@ __device__ EigWs eig_ws(double *base, int n, double *hv, double *A = nullptr) {
 }
 
 // Tridiagonalise E.A (symmetric, loaded) and diagonalise T by implicit QL.
-// On return Z (column-major) overwrites E.A and the eigenvalues are in E.dd.
+// On return Z (column j at E.A[j E.pa ..]) overwrites E.A and the eigenvalues are in E.dd.
 // (d, e) and (c, s) pairs of the QL solve, 16-byte aligned so that a pair moves in one
 // LDS access
 struct __attribute__((aligned(16))) Pair { double x, y; };
@@ -908,8 +918,19 @@ __device__ void tri_reduce_wave(const EigWs &E) {
     const double K2 = beta * wave_sum(act ? v * p : 0.0);   // 2K = beta v^T p
     __threadfence_block();
     if (act) {                                            // A_t -= v p^T + p v^T - 2K v v^T
+      // in chunks of 8: all loads of a chunk are issued before its stores (a store to row[]
+      // could alias a later load of pp[] or vv[] as far as the compiler knows, so a plain
+      // loop would wait out the LDS latency on every element)
       const double vk = v * K2;
-      for (int b = 0; b < m; ++b) row[b] -= fma(v, pp[b], fma(p, vv[b], -vk * vv[b]));
+      int b = 0;
+      for (; b + 8 <= m; b += 8) {
+        double x[8], pb[8], vb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) { x[u] = row[b + u]; pb[u] = pp[b + u]; vb[u] = vv[b + u]; }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) row[b + u] = x[u] - fma(v, pb[u], fma(p, vb[u], -vk * vb[u]));
+      }
+      for (; b < m; ++b) row[b] -= fma(v, pp[b], fma(p, vv[b], -vk * vv[b]));
     }
     __threadfence_block();
   }
@@ -946,7 +967,7 @@ __device__ void tri_reduce_wave(const EigWs &E) {
 // Eigenvector blocks alternate between two n x n buffers whose entries outside the
 // current blocks stay zero.
 constexpr int kDcMax = 64;
-__host__ __device__ constexpr int dc_lds_doubles(int n) { return n * n + n * (n + 1) + 16 * n; }
+__host__ __device__ constexpr int dc_lds_doubles(int n) { return 2 * n * (n + 1) + 16 * n; }
 
 struct DcWs {
   double *Zb, *W;                                  // second eigenvector buffer; merge matrices
@@ -956,8 +977,8 @@ struct DcWs {
 
 __device__ DcWs dc_ws(double *base, int n) {
   DcWs W;
-  W.Zb = base;
-  W.W = base + n * n;                              // n x (n + 1): odd pitch
+  W.Zb = base;                                     // n x (n + 1), as Z
+  W.W = base + n * (n + 1);                        // n x (n + 1): odd pitch
   double *v = W.W + n * (n + 1);
   W.D = v; W.z = v + n; W.dk = v + 2 * n; W.zk = v + 3 * n; W.tau = v + 4 * n; W.zh = v + 5 * n;
   W.rc = v + 6 * n; W.rs = v + 7 * n;
@@ -1108,6 +1129,7 @@ __device__ double dc_root(const double *dk, const double *zk, int K, int t, doub
 // graded matrix far more than a QL solve does).
 __device__ void dc_deflate(double *Z, const double *dd, const double *ee, const DcWs &W, int n, int S) {
   constexpr double kEps = 2.220446049250313e-16;
+  const int zpitch = n + 1;                         // column pitch of Z
   const int lane = threadIdx.x & 63, g = S < 64 ? S : 64;
   const int base = (lane / g) * g, lo = (lane / g) * S, t = lane - base;
   const int m = lo + S / 2, hi = lo + S < n ? lo + S : n;
@@ -1120,7 +1142,7 @@ __device__ void dc_deflate(double *Z, const double *dd, const double *ee, const 
     rho = 2.0 * fabs(e);
     if (act) {                                      // z: last row of Q1, first row of Q2
       Dt = dd[lo + t];
-      zt = (t < n1 ? Z[(lo + t) * n + (m - 1)] : copysign(1.0, e) * Z[(lo + t) * n + m]) * 0.70710678118654752440;
+      zt = (t < n1 ? Z[(lo + t) * zpitch + (m - 1)] : copysign(1.0, e) * Z[(lo + t) * zpitch + m]) * 0.70710678118654752440;
       W.D[lo + t] = Dt;
       W.z[lo + t] = zt;
     }
@@ -1193,7 +1215,7 @@ __device__ void dc_deflate(double *Z, const double *dd, const double *ee, const 
   if (act) {                                        // deflation rotations on row lo+t of Q
     const int row = lo + t;
     for (int r = 0; r < nr; ++r) {
-      double *qa = Z + (lo + W.rj[lo + r]) * n + row, *qb = Z + (lo + W.ri[lo + r]) * n + row;
+      double *qa = Z + (lo + W.rj[lo + r]) * zpitch + row, *qb = Z + (lo + W.ri[lo + r]) * zpitch + row;
       const double c = W.rc[lo + r], sn = W.rs[lo + r], x = *qa, y = *qb;
       *qa = c * x + sn * y;
       *qb = -sn * x + c * y;
@@ -1219,7 +1241,7 @@ __device__ __forceinline__ DcPos dc_pos(const DcWs &W, int n, int S, int q) {
 }
 
 // Eigenpairs of the tridiagonal (E.dd, E.ee) by divide and conquer: eigenvalues in E.dd
-// (unordered), eigenvectors in E.A as Z (column j at E.A[j n ..]), as the QL solve leaves them.
+// (unordered), eigenvectors in E.A as Z (column j at E.A[j (n+1) ..]), as the QL solve leaves them.
 // Per level: wave 0 deflates every merge; then groups of L lanes (one per index of the
 // level) find the roots and write delta_i - lam_t (column t of the merge's block of W, odd
 // pitch pw), recompute z, form and normalise the vectors u_t; then the workgroup multiplies.
@@ -1228,10 +1250,10 @@ __device__ void tri_dc(const EigWs &E, double *base) {
   const int L = n <= 16 ? 16 : (n <= 32 ? 8 : 4);  // lanes per index of a level
   const int q = tid / L, sub = tid % L;
   const DcWs W = dc_ws(base, n);
-  const int pw = n + 1;
+  const int pw = n + 1, zp = n + 1;                 // pitches of the merge matrices and of Z
   double *Za = E.A, *Zb = W.Zb;
-  for (int e = tid; e < n * n; e += kThreads) {
-    Za[e] = (e / n == e % n) ? 1.0 : 0.0;
+  for (int e = tid; e < n * zp; e += kThreads) {
+    Za[e] = (e / zp == e % zp) ? 1.0 : 0.0;
     Zb[e] = 0.0;
   }
   for (int i = tid; i < n; i += kThreads)           // the tears: leaves d_i - |e_i-1| - |e_i|
@@ -1268,14 +1290,19 @@ __device__ void tri_dc(const EigWs &E, double *base) {
     if (q < n && P.t < P.s) {                       // column t of u, normalised; the eigenvalues
       const int t = P.t, K = P.K;
       if (t < K) {
-        double nrm = 0.0;
-        for (int i = sub; i < K; i += L) {
-          const double u = W.zh[P.lo + i] * rcp_nr(U[t * pw + i]);
-          U[t * pw + i] = u;
-          nrm = fma(u, u, nrm);
+        double nrm = 0.0, uv[16];                   // K <= 64 and L >= 4: at most 16 per lane
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int i = sub + c * L;
+          uv[c] = i < K ? W.zh[P.lo + i] * rcp_nr(U[t * pw + i]) : 0.0;
+          nrm = fma(uv[c], uv[c], nrm);
         }
         const double sc = 1.0 / sqrt(lsum(nrm, L));
-        for (int i = sub; i < K; i += L) U[t * pw + i] *= sc;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int i = sub + c * L;
+          if (i < K) U[t * pw + i] = uv[c] * sc;
+        }
       }
       if (sub == 0) E.dd[P.lo + t] = t < K ? W.tau[P.lo + t] : W.D[P.lo + W.defl[P.lo + (t - K)]];
     }
@@ -1295,28 +1322,28 @@ __device__ void tri_dc(const EigWs &E, double *base) {
         const double *Ub = W.W + lo * pw + lo;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         for (int i = 0; i < K; ++i) {
-          const double qv = Zc[(lo + W.kept[lo + i]) * n + lo + row];
+          const double qv = Zc[(lo + W.kept[lo + i]) * zp + lo + row];
           a0 = fma(qv, Ub[j0 * pw + i], a0);
           if (jn > 1) a1 = fma(qv, Ub[(j0 + 1) * pw + i], a1);
           if (jn > 2) a2 = fma(qv, Ub[(j0 + 2) * pw + i], a2);
           if (jn > 3) a3 = fma(qv, Ub[(j0 + 3) * pw + i], a3);
         }
-        double *out = Zn + (lo + j0) * n + lo + row;
+        double *out = Zn + (lo + j0) * zp + lo + row;
         out[0] = a0;
-        if (jn > 1) out[n] = a1;
-        if (jn > 2) out[2 * n] = a2;
-        if (jn > 3) out[3 * n] = a3;
+        if (jn > 1) out[zp] = a1;
+        if (jn > 2) out[2 * zp] = a2;
+        if (jn > 3) out[3 * zp] = a3;
       }
       for (int j = j0 + jn; j < j0 + 4 && j < s; ++j) {          // deflated (or unmerged) columns
         const int src = merge ? lo + W.defl[lo + (j - K)] : lo + j;
-        Zn[(lo + j) * n + lo + row] = Zc[src * n + lo + row];
+        Zn[(lo + j) * zp + lo + row] = Zc[src * zp + lo + row];
       }
     }
     __syncthreads();
     double *tmp = Zc; Zc = Zn; Zn = tmp;
   }
   if (Zc != Za) {
-    for (int e = tid; e < n * n; e += kThreads) Za[e] = Zc[e];
+    for (int e = tid; e < n * zp; e += kThreads) Za[e] = Zc[e];
     __syncthreads();
   }
 }
@@ -1426,7 +1453,7 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed, double *dcws 
   }
 
   double *Z = A;
-  for (int e = tid; e < n * n; e += kThreads) Z[e] = (e / n == e % n) ? 1.0 : 0.0;
+  for (int e = tid; e < n * pa; e += kThreads) Z[e] = (e / pa == e % pa) ? 1.0 : 0.0;
   // Implicit QL, split between a producer and consumers. Wave 0 runs the chase on its
   // own LDS copy of (d, e) (a sweep step reads index i and writes i+1, so the next
   // step's reads are issued one step ahead) and records the (c, s) of every rotation
@@ -1521,17 +1548,17 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed, double *dcws 
     if (wave > 0 && cnt > 0) {                       // apply the iteration's rotations to rows crow
       const Pair *rb = rot + n * b;
       for (int row = crow; row < n; row += kThreads - 64) {
-        double zc = Z[m * n + row];                  // current value of column i+1
-        double zn = Z[(m - 1) * n + row];            // column i, fetched one step ahead
+        double zc = Z[m * pa + row];                 // current value of column i+1
+        double zn = Z[(m - 1) * pa + row];           // column i, fetched one step ahead
         for (int j = 0; j < cnt; ++j) {
           const int i = m - 1 - j;
           const double zi = zn;
-          if (j + 1 < cnt) zn = Z[(i - 1) * n + row];
+          if (j + 1 < cnt) zn = Z[(i - 1) * pa + row];
           const Pair cs = rb[j];
-          Z[(i + 1) * n + row] = cs.y * zi + cs.x * zc;
+          Z[(i + 1) * pa + row] = cs.y * zi + cs.x * zc;
           zc = cs.x * zi - cs.y * zc;
         }
-        Z[(m - cnt) * n + row] = zc;
+        Z[(m - cnt) * pa + row] = zc;
       }
     }
   }
@@ -1587,7 +1614,7 @@ constexpr int kWY = 4;
 __device__ void back_transform_quads(const EigWs &E, int k) {
   const int n = E.n, tid = threadIdx.x, sub = tid & 3, t = tid >> 2;
   if (t < k) {                               // every lane of the quad takes this branch
-    double *z = E.A + E.isrt[t] * n;
+    double *z = E.A + E.isrt[t] * E.pa;
     for (int j = n - 3; j >= 0; --j) {
       const double beta = E.hv[int64_t(n) * n + j];
       if (beta == 0.0) continue;             // the same j and beta in every lane
@@ -1602,7 +1629,16 @@ __device__ void back_transform_quads(const EigWs &E, int k) {
       }
       if (i < m) a0 = fma(v[i], zz[i], a0);
       const double w = beta * quad_sum(a0 + a1);
-      for (int r = sub; r < m; r += 4) zz[r] = fma(-w, v[r], zz[r]);
+      int r = sub;                           // loads of 4 rows issued before their stores
+      for (; r + 12 < m; r += 16) {
+        const double v0 = v[r], v1 = v[r + 4], v2 = v[r + 8], v3 = v[r + 12];
+        const double z0 = zz[r], z1 = zz[r + 4], z2 = zz[r + 8], z3 = zz[r + 12];
+        zz[r] = fma(-w, v0, z0);
+        zz[r + 4] = fma(-w, v1, z1);
+        zz[r + 8] = fma(-w, v2, z2);
+        zz[r + 12] = fma(-w, v3, z3);
+      }
+      for (; r < m; r += 4) zz[r] = fma(-w, v[r], zz[r]);
     }
   }
   __syncthreads();
@@ -1637,7 +1673,7 @@ __device__ void back_transform(const EigWs &E, int k) {
     double *Vnext = E.wq + (cur ^ 1) * kWY * n;
     // phase 1: w_t = V^T z_t (tasks t < k) and the Gram entries (tasks k .. k+b-2: v_c . v_l, l < c)
     for (int task = grp; task < k + b - 1; task += kThreads / 4) {
-      const double *z = task < k ? Z + E.isrt[task] * n + jlo + 1 : Vb + (task - k + 1) * n;
+      const double *z = task < k ? Z + E.isrt[task] * E.pa + jlo + 1 : Vb + (task - k + 1) * n;
       double a[kWY] = {0.0, 0.0, 0.0, 0.0};
       for (int i = sub; i < mlo; i += 4) {
         const double zi = z[i];
@@ -1690,7 +1726,7 @@ __device__ void back_transform(const EigWs &E, int k) {
         for (int c = 0; c < kWY; ++c) acc += T[r][c] * w[c];
         u[r] = acc;
       }
-      double *z = Z + E.isrt[t] * n + jlo + 1;
+      double *z = Z + E.isrt[t] * E.pa + jlo + 1;
       for (int i = lane; i < mlo; i += 64) {
         double acc = 0.0;
 #pragma unroll
@@ -1954,7 +1990,7 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
       double *U = ws + op.c;
       for (int e = tid; e < n * k; e += kThreads) {
         const int i = e / k, j = e % k;
-        const double *y = E.A + E.isrt[j] * p;
+        const double *y = E.A + E.isrt[j] * E.pa;
         double x = 0.0, wy = 0.0;
         for (int c = 0; c < p; ++c) { x += V[i * p + c] * y[c]; wy += W[i * p + c] * y[c]; }
         const double r = wy - E.wsrt[j] * x;
@@ -2061,7 +2097,7 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
   double *U = ws + op.c;                  // U[j][i], j < k kept vectors, i < n components
   for (int e = tid; e < n * k; e += kThreads) {
     const int j = e / n, i = e % n;
-    U[int64_t(j) * ld + i] = E.A[E.isrt[j] * n + i];
+    U[int64_t(j) * ld + i] = E.A[E.isrt[j] * E.pa + i];
   }
   __syncthreads();
   if (kp.hx && warm) harvest_rows(op, ws, n, ld, k, kp, E.red, E.flag + 2);
@@ -2569,11 +2605,71 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_grid_piped_kernel(const NetD
   gemm_grid_piped(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc);
 }
 
+// FP64 chip-wide contraction of at most 32 rows and at most KT-deep K over a long N (the
+// 3D environments' products with a site tensor): about two flops per byte, so it is bound
+// by streaming B (K x N) in and C (M x N) out, not by the matrix cores. A (M x KT) and the
+// offsets are staged in LDS; each thread takes CPT columns at a time in a grid stride
+// (consecutive threads, consecutive columns), loads their K values of B, and writes M
+// outputs per column; every LDS read of A serves CPT columns.
+template <int KT, int CPT>
+__global__ __launch_bounds__(kThreads) void gemm_stream_kernel(const NetDev *__restrict__ ndp, int64_t i) {
+  __shared__ double As[kStreamMaxM * KT];
+  __shared__ int32_t kB[KT];
+  __shared__ int64_t rC[kStreamMaxM];
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  const int M = box_eff(op.bm), N = box_eff(op.bnb), K = box_eff(op.bk_);
+  const int64_t NS = op.bn.n;
+  const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
+  const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
+  double *C = nd.ws + op.c;
+  const int32_t *tab = nd.tab;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) nd.sc->flops += 2LL * M * N * K;
+  for (int e = tid; e < kStreamMaxM * KT; e += kThreads) {
+    const int m = e / KT, k = e % KT;
+    As[e] = (m < M && k < K) ? A[map_off(tab, op.am, box_conv(op.bm, m)) + tab[op.ak + box_conv(op.bk_, k)]] : 0.0;
+  }
+  for (int k = tid; k < KT; k += kThreads) kB[k] = k < K ? tab[op.bk + box_conv(op.bk_, k)] : 0;
+  for (int m = tid; m < kStreamMaxM; m += kThreads) rC[m] = m < M ? int64_t(box_conv(op.bm, m)) * NS : 0;
+  __syncthreads();
+  const int64_t T = int64_t(gridDim.x) * kThreads;
+  for (int64_t n0 = int64_t(blockIdx.x) * kThreads + tid; n0 < N; n0 += T * CPT) {
+    int32_t sn[CPT];
+    double b[CPT][KT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int64_t n = n0 + c * T;
+      sn[c] = n < N ? box_conv(op.bnb, int32_t(n)) : -1;
+      const int64_t boff = sn[c] >= 0 ? map_off(tab, op.bn, sn[c]) : 0;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) b[c][k] = (sn[c] >= 0 && k < K) ? B[boff + kB[k]] : 0.0;
+    }
+    for (int m = 0; m < M; ++m) {
+      double acc[CPT];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) acc[c] = 0.0;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const double a = As[m * KT + k];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) acc[c] = fma(a, b[c][k], acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < CPT; ++c)
+        if (sn[c] >= 0) C[rC[m] + sn[c]] = acc[c];
+    }
+  }
+}
+
 // FP64 chip-wide GEMM whose offsets do not fit the pipelined path: the tiled GEMM with
 // k offsets cached up to K = kGridKCache (the 3D environments contract over K = 8192)
 constexpr int kGridKCache = 8192;
 constexpr int kGridTilesLds = 2 * kTK * kPitch + kGridKCache;
-__global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__restrict__ ndp, int64_t i) {
+__global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__restrict__ ndp, int64_t i, int kchunks,
+                                                              double *kpart) {
   __shared__ double lds[kGridTilesLds > kGridLdsAll ? kGridTilesLds : kGridLdsAll];
   __shared__ Op s_op;
   const NetDev nd = *ndp;
@@ -2581,8 +2677,27 @@ __global__ __launch_bounds__(kThreads) void gemm_grid_kernel(const NetDev *__res
   const Op &op = s_op;
   const double *A = ((op.flags & F_A_CONST) ? nd.cst : nd.ws) + op.a;
   const double *B = ((op.flags & F_B_CONST) ? nd.cst : nd.ws) + op.b;
-  if (gemm_grid_piped(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc)) return;
-  gemm_tiles_k<kGridKCache>(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc);
+  if (kchunks <= 1 && gemm_grid_piped(op, A, B, nd.ws + op.c, nd.tab, lds, nd.sc)) return;
+  gemm_tiles_k<kGridKCache>(op, A, B, nd.ws + op.c, nd.tab, lds, blockIdx.x, gridDim.x, nd.sc, kchunks,
+                            kchunks > 1 ? kpart : nullptr);
+}
+
+// Second pass of a split-K GEMM: C = the sum of the kchunks partial products, in order.
+__global__ __launch_bounds__(kThreads) void gemm_kreduce_kernel(const NetDev *__restrict__ ndp, int64_t i, int kchunks,
+                                                                const double *__restrict__ kpart) {
+  __shared__ Op s_op;
+  const NetDev nd = *ndp;
+  stage_op(nd, i, s_op);
+  const Op &op = s_op;
+  const int M = box_eff(op.bm), N = box_eff(op.bnb);
+  const int64_t NS = op.bn.n, MN = int64_t(M) * N;
+  double *C = nd.ws + op.c;
+  for (int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x; e < MN; e += int64_t(gridDim.x) * kThreads) {
+    double s = 0.0;
+    for (int p = 0; p < kchunks; ++p) s += kpart[p * MN + e];
+    const int row = int(e / N), col = int(e - int64_t(row) * N);
+    C[int64_t(box_conv(op.bm, row)) * NS + box_conv(op.bnb, col)] = s;
+  }
 }
 
 // max |x| over this workgroup's share of the valid box -> partial[blockIdx.x]
@@ -2652,7 +2767,8 @@ hipError_t launch_interp_range(const NetDev *nd_dev, int64_t first, int64_t last
 }
 
 hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, bool piped,
-                            unsigned short *planes, int split_blocks, hipStream_t stream) {
+                            unsigned short *planes, int split_blocks, int kchunks, double *kpart, int stream_k,
+                            hipStream_t stream) {
   if (split == 1 || split == 2) {
     if (!planes || split_blocks < 1) return hipErrorInvalidValue;
     if (split == 1) {
@@ -2664,10 +2780,26 @@ hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int spl
       hipLaunchKernelGGL(gemm_presplit_kernel<2>, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i,
                          (const unsigned short *)planes);
     }
-  } else if (piped)
+  } else if (stream_k > 0) {
+    switch (stream_k) {
+      case 4: hipLaunchKernelGGL((gemm_stream_kernel<4, 8>), dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i); break;
+      case 8: hipLaunchKernelGGL((gemm_stream_kernel<8, 4>), dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i); break;
+      case 16: hipLaunchKernelGGL((gemm_stream_kernel<16, 2>), dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i); break;
+      case 32: hipLaunchKernelGGL((gemm_stream_kernel<32, 1>), dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (piped) {
     hipLaunchKernelGGL(gemm_grid_piped_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);
-  else
-    hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i);
+  } else if (kchunks > 1) {
+    if (!kpart) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i, kchunks, kpart);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gemm_kreduce_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i, kchunks,
+                       (const double *)kpart);
+  } else {
+    hipLaunchKernelGGL(gemm_grid_kernel, dim3(blocks), dim3(kThreads), 0, stream, nd_dev, i, 1, (double *)nullptr);
+  }
   return hipGetLastError();
 }
 

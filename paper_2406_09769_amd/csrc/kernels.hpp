@@ -79,8 +79,38 @@ inline int split_grid_blocks(int64_t rows, int64_t cols, int64_t K) {
   const int64_t blocks = ((rows + cols) * ((K + 15) / 16) + 255) / 256;
   return int(blocks < kGridBlocks ? (blocks < 1 ? 1 : blocks) : kGridBlocks);
 }
+// Split K: an FP64 chip-wide GEMM that does not run pipelined and has too few 64 x 64
+// output tiles to fill the chip cuts K into kchunks parts (a power of two, each at least
+// 128 deep) so that tiles x kchunks work items reach about 512 (more parts measured slower:
+// 382 against 331 us per call with up to 2048); every work item writes its
+// partial tile to kpart (kchunks x rows x cols doubles of device scratch at the runtime
+// extents), and a second pass adds the parts in a fixed order into C (reproducible).
+inline int grid_kchunks(int64_t rows, int64_t cols, int64_t K) {
+  const int64_t tiles = ((rows + 63) / 64) * ((cols + 63) / 64);
+  int64_t c = 1;
+  while (2 * c * tiles <= 512 && K >= 2 * c * 128) c *= 2;
+  return int(c);
+}
+inline int64_t grid_kpart_doubles(int64_t rows, int64_t cols, int64_t K) {
+  const int c = grid_kchunks(rows, cols, K);
+  return c > 1 ? int64_t(c) * rows * cols : 0;
+}
+// Streaming: an FP64 chip-wide GEMM of at most kStreamMaxM static rows and at most 32
+// static K over at least kStreamMinN columns runs as a VALU kernel streaming B and C
+// (stream_k = its K class 4, 8, 16 or 32; 0 = not streamed), over stream_blocks workgroups.
+constexpr int kStreamMaxM = 32;
+constexpr int64_t kStreamMinN = int64_t(1) << 16;
+inline int stream_kclass(int64_t rows, int64_t cols, int64_t K) {
+  if (rows > kStreamMaxM || K > 32 || cols < kStreamMinN) return 0;
+  return K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 16 ? 16 : 32));
+}
+inline int stream_blocks(int64_t cols) {
+  const int64_t b = (cols + 4 * 256 - 1) / (4 * 256);
+  return int(b < kGridBlocks ? (b < 1 ? 1 : b) : kGridBlocks);
+}
 hipError_t launch_gemm_grid(const NetDev *nd_dev, int64_t i, int blocks, int split, bool piped,
-                            unsigned short *planes, int split_blocks, hipStream_t stream);
+                            unsigned short *planes, int split_blocks, int kchunks, double *kpart, int stream_k,
+                            hipStream_t stream);
 hipError_t launch_rescale_grid(const NetDev *nd_dev, int64_t i, int blocks, double *partial, hipStream_t stream);
 
 // Scratch of the allocation-free entry point: a static device array of this many bytes

@@ -173,13 +173,19 @@ def _operands(M, N, K, layout, rng):
 
 CHIP_SHAPES = [(1, 1, 1), (3, 257, 5), (16, 513, 17), (20, 300, 40), (32, 129, 33), (64, 64, 16), (130, 200, 37),
                (300, 70, 1100), (700, 65, 600), (70, 90, 2100), (40, 33, 10300)]
+# at least 2^16 columns, at most 32 rows and 32-deep K: the streaming kernel (one shape per K
+# class, ragged column counts); the last two take the split-K path (few tiles, long K)
+STREAM_SHAPES = [(4, 65536, 3), (8, 70001, 8), (32, 65539, 16), (17, 66000, 32), (33, 65536, 8), (32, 32, 8192),
+                 (32, 2048, 2048)]
 
 
 @pytest.mark.parametrize("layout", ["kn", "mk"])
-@pytest.mark.parametrize("M,N,K", CHIP_SHAPES)
+@pytest.mark.parametrize("M,N,K", CHIP_SHAPES + STREAM_SHAPES)
 def test_gemm_chip_wide_fp64(T, M, N, K, layout):
     """The launch of a contraction too large for one workgroup (row + k offsets within
-    the LDS cache: pipelined tiles; else the plain tiled kernel), against numpy."""
+    the LDS cache: pipelined tiles; few rows and shallow K over many columns: the streaming
+    kernel; else the plain tiled kernel, with K split into parts when few tiles would
+    leave the chip idle), against numpy."""
     rng = np.random.default_rng(M * 31 + N * 7 + K)
     A, B = _operands(M, N, K, layout, rng)
     C = T.tn_debug_gemm(A, B, chip_wide=True)
