@@ -83,7 +83,7 @@ typedef enum {
 
 typedef enum {
   TN_TRIDIAG_AUTO = 0,  /* tridiagonal eigensolve by divide and conquer for density matrices
-                           of order up to 64 (Cuppen's tearing, eigenvectors from the roots by
+                           of order up to 128 (Cuppen's tearing, eigenvectors from the roots by
                            the Loewner formula of Gu and Eisenstat), implicit QL above */
   TN_TRIDIAG_QL = 1     /* implicit QL with Wilkinson shifts for every order */
 } tn_tridiag;

@@ -1091,7 +1091,7 @@ int tn_debug_eig(const double *L, int32_t n, int32_t ucols, int32_t rest, const 
   int64_t usz = (int64_t(n) * ucols + 31) / 32 * 32;
   op.b = lsz + usz;
   op.flags |= tn::F_V_GLOBAL;
-  std::vector<double> ws(lsz + usz + 2 * (np * np + np), 0.0);
+  std::vector<double> ws(lsz + usz + 3 * (np * np + np), 0.0);   // the scratch the planner gives
   std::memcpy(ws.data(), L, size_t(n) * n * 8);
   if (o.tridiag != TN_TRIDIAG_AUTO && o.tridiag != TN_TRIDIAG_QL) return fail(TN_EINVAL, "unknown tridiagonal solver");
   tn::KeepParams kp{o.tau_rel, o.tau_deg, tn::kClusterFloor * o.tau_rel};

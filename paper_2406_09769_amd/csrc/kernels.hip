@@ -965,9 +965,16 @@ __device__ void tri_reduce_wave(const EigWs &E) {
 //    u_t = (zh_i / (delta_i - lam_t))_i normalised;
 //  * the merged eigenvectors are Q u_t (kept) and the deflated columns of Q.
 // Eigenvector blocks alternate between two n x n buffers whose entries outside the
-// current blocks stay zero.
-constexpr int kDcMax = 64;
-__host__ __device__ constexpr int dc_lds_doubles(int n) { return 2 * n * (n + 1) + 16 * n; }
+// current blocks stay zero. Up to order kDcLdsMax both buffers and the merge matrices are in
+// LDS; up to kDcMax the second buffer and the merge matrices are in the op's global scratch.
+constexpr int kDcLdsMax = 64;
+constexpr int kDcMax = 128;
+__host__ __device__ constexpr int dc_vec_doubles(int n) { return 8 * n + (9 * n + 1) / 2; }
+__host__ __device__ constexpr int dc_lds_doubles(int n) { return 2 * n * (n + 1) + dc_vec_doubles(n); }
+
+struct DcBufs {
+  double *vec, *zb, *wm;   // per-index vectors (LDS), second eigenvector buffer, merge matrices
+};
 
 struct DcWs {
   double *Zb, *W;                                  // second eigenvector buffer; merge matrices
@@ -975,11 +982,11 @@ struct DcWs {
   int *perm, *kept, *defl, *org, *rj, *ri, *cnt;   // per index; cnt: K, deflated, rotations at lo
 };
 
-__device__ DcWs dc_ws(double *base, int n) {
+__device__ DcWs dc_ws(const DcBufs &b, int n) {
   DcWs W;
-  W.Zb = base;                                     // n x (n + 1), as Z
-  W.W = base + n * (n + 1);                        // n x (n + 1): odd pitch
-  double *v = W.W + n * (n + 1);
+  W.Zb = b.zb;                                     // n x (n + 1), as Z
+  W.W = b.wm;                                      // n x (n + 1): odd pitch
+  double *v = b.vec;
   W.D = v; W.z = v + n; W.dk = v + 2 * n; W.zk = v + 3 * n; W.tau = v + 4 * n; W.zh = v + 5 * n;
   W.rc = v + 6 * n; W.rs = v + 7 * n;
   int *iv = reinterpret_cast<int *>(v + 8 * n);
@@ -994,17 +1001,18 @@ __device__ __forceinline__ double group_max(double v, int g) {
   return v;
 }
 
-// sum and product over aligned groups of L lanes, L in {4, 8, 16} (all lanes of a group
+// sum and product over aligned groups of L lanes, L in {2, 4, 8, 16} (all lanes of a group
 // active); every lane of the group gets the same value
 __device__ __forceinline__ double lsum(double v, int L) {
-  v = quad_sum(v);
+  v += dpp_f64<kDppQuadXor1>(v);
+  if (L >= 4) v += dpp_f64<kDppQuadXor2>(v);
   if (L >= 8) v += dpp_f64<kDppRowHalfMirror>(v);
   if (L >= 16) v += dpp_f64<kDppRowMirror>(v);
   return v;
 }
 __device__ __forceinline__ double lprod(double v, int L) {
   v *= dpp_f64<kDppQuadXor1>(v);
-  v *= dpp_f64<kDppQuadXor2>(v);
+  if (L >= 4) v *= dpp_f64<kDppQuadXor2>(v);
   if (L >= 8) v *= dpp_f64<kDppRowHalfMirror>(v);
   if (L >= 16) v *= dpp_f64<kDppRowMirror>(v);
   return v;
@@ -1121,17 +1129,19 @@ __device__ double dc_root(const double *dk, const double *zk, int K, int t, doub
   return tau;
 }
 
-// Wave 0, lane groups of width S (one merge each, blocks [lo, lo + S)): gather D and z,
+// Lane groups of width S (one merge each, blocks [lo, lo + S)): gather D and z,
 // order D, deflate, rotate the columns of Z the deflation pairs, and list the poles (dk, zk)
 // of the remaining secular equation. cnt[3lo] = K roots, cnt[3lo+1] deflated columns.
 // tol = 8 eps max(|D|, rho |z|) of the merge: each deflation perturbs the merged block by
 // at most that (a tolerance from ||T|| instead would perturb the small eigenvalues of a
 // graded matrix far more than a QL solve does).
-__device__ void dc_deflate(double *Z, const double *dd, const double *ee, const DcWs &W, int n, int S) {
+// Merges of width S <= 64 only: the calling wave takes those whose block starts in
+// [64 win, 64 win + 64).
+__device__ void dc_deflate(double *Z, const double *dd, const double *ee, const DcWs &W, int n, int S, int win) {
   constexpr double kEps = 2.220446049250313e-16;
   const int zpitch = n + 1;                         // column pitch of Z
-  const int lane = threadIdx.x & 63, g = S < 64 ? S : 64;
-  const int base = (lane / g) * g, lo = (lane / g) * S, t = lane - base;
+  const int lane = threadIdx.x & 63, g = S;
+  const int base = (lane / g) * g, lo = 64 * win + (lane / g) * S, t = lane - base;
   const int m = lo + S / 2, hi = lo + S < n ? lo + S : n;
   const bool merge = lo < n && m < hi;
   const int s = merge ? hi - lo : 0, n1 = m - lo;
@@ -1224,6 +1234,75 @@ __device__ void dc_deflate(double *Z, const double *dd, const double *ee, const 
   if (t < K) { W.dk[lo + t] = W.D[lo + W.kept[lo + t]]; W.zk[lo + t] = W.z[lo + W.kept[lo + t]]; }
 }
 
+// The merge of width 128 (orders 65 to 128): one merge of s = n elements, two per lane of
+// the calling wave; the deflation scan runs in one lane.
+__device__ __noinline__ void dc_deflate_big(double *Z, const double *dd, const double *ee, const DcWs &W, int n) {
+  constexpr double kEps = 2.220446049250313e-16;
+  const int zp = n + 1, lane = threadIdx.x & 63, m = 64, s = n;
+  const double e = ee[m - 1], rho = 2.0 * fabs(e);
+  double dmx = 0.0, zmx = 0.0;
+  for (int t = lane; t < s; t += 64) {             // z: last row of Q1, first row of Q2
+    const double Dt = dd[t];
+    const double zt = (t < m ? Z[t * zp + (m - 1)] : copysign(1.0, e) * Z[t * zp + m]) * 0.70710678118654752440;
+    W.D[t] = Dt;
+    W.z[t] = zt;
+    dmx = fmax(dmx, fabs(Dt));
+    zmx = fmax(zmx, fabs(zt));
+  }
+  const double tol = 8.0 * kEps * fmax(wave_max(dmx), rho * wave_max(zmx));
+  __threadfence_block();
+  for (int t = lane; t < s; t += 64) {             // ascending order, ties by index
+    const double Dt = W.D[t];
+    int r = 0;
+    for (int u = 0; u < s; ++u) {
+      const double du = W.D[u];
+      r += (du < Dt) || (du == Dt && u < t);
+    }
+    W.perm[r] = t;
+  }
+  __threadfence_block();
+  if (lane == 0) {
+    int K = 0, nd = 0, nr = 0, cand = -1;
+    if (rho == 0.0) {
+      for (int p = 0; p < s; ++p) W.defl[nd++] = W.perm[p];
+    } else {
+      for (int p = 0; p < s; ++p) {
+        const int i = W.perm[p];
+        const double zi = W.z[i];
+        if (rho * fabs(zi) <= tol) { W.defl[nd++] = i; continue; }
+        if (cand < 0) { cand = i; continue; }
+        const double zc = W.z[cand];
+        const double tt = hypot(zc, zi), c = zi / tt, sn = -zc / tt;
+        const double dc = W.D[cand], di = W.D[i];
+        if (fabs((di - dc) * c * sn) <= tol) {
+          W.rj[nr] = cand; W.ri[nr] = i; W.rc[nr] = c; W.rs[nr] = sn; ++nr;
+          W.D[cand] = dc * c * c + di * sn * sn;
+          W.D[i] = dc * sn * sn + di * c * c;
+          W.z[i] = tt;
+          W.z[cand] = 0.0;
+          W.defl[nd++] = cand;
+        } else {
+          W.kept[K++] = cand;
+        }
+        cand = i;
+      }
+      if (cand >= 0) W.kept[K++] = cand;
+    }
+    W.cnt[0] = K; W.cnt[1] = nd; W.cnt[2] = nr;
+  }
+  __threadfence_block();
+  const int K = W.cnt[0], nr = W.cnt[2];
+  for (int row = lane; row < n; row += 64) {       // deflation rotations on the rows of Q
+    for (int r = 0; r < nr; ++r) {
+      double *qa = Z + W.rj[r] * zp + row, *qb = Z + W.ri[r] * zp + row;
+      const double c = W.rc[r], sn = W.rs[r], x = *qa, y = *qb;
+      *qa = c * x + sn * y;
+      *qb = -sn * x + c * y;
+    }
+  }
+  for (int t = lane; t < K; t += 64) { W.dk[t] = W.D[W.kept[t]]; W.zk[t] = W.z[W.kept[t]]; }
+}
+
 // The merge and the position within it that quad q (= index q of the level) stands for.
 struct DcPos {
   int lo, t, s, K;
@@ -1242,14 +1321,14 @@ __device__ __forceinline__ DcPos dc_pos(const DcWs &W, int n, int S, int q) {
 
 // Eigenpairs of the tridiagonal (E.dd, E.ee) by divide and conquer: eigenvalues in E.dd
 // (unordered), eigenvectors in E.A as Z (column j at E.A[j (n+1) ..]), as the QL solve leaves them.
-// Per level: wave 0 deflates every merge; then groups of L lanes (one per index of the
+// Per level: wave 0 (and wave 1 above order 64) deflates every merge; then groups of L lanes (one per index of the
 // level) find the roots and write delta_i - lam_t (column t of the merge's block of W, odd
 // pitch pw), recompute z, form and normalise the vectors u_t; then the workgroup multiplies.
-__device__ void tri_dc(const EigWs &E, double *base) {
+__device__ void tri_dc(const EigWs &E, const DcBufs &bufs) {
   const int n = E.n, tid = threadIdx.x, wave = tid >> 6;
-  const int L = n <= 16 ? 16 : (n <= 32 ? 8 : 4);  // lanes per index of a level
+  const int L = n <= 16 ? 16 : (n <= 32 ? 8 : (n <= 64 ? 4 : 2));   // lanes per index of a level
   const int q = tid / L, sub = tid % L;
-  const DcWs W = dc_ws(base, n);
+  const DcWs W = dc_ws(bufs, n);
   const int pw = n + 1, zp = n + 1;                 // pitches of the merge matrices and of Z
   double *Za = E.A, *Zb = W.Zb;
   for (int e = tid; e < n * zp; e += kThreads) {
@@ -1261,7 +1340,11 @@ __device__ void tri_dc(const EigWs &E, double *base) {
   __syncthreads();
   double *Zc = Za, *Zn = Zb;
   for (int S = 2; S / 2 < n; S *= 2) {
-    if (wave == 0) dc_deflate(Zc, E.dd, E.ee, W, n, S);
+    if (S <= 64) {
+      if (64 * wave < n) dc_deflate(Zc, E.dd, E.ee, W, n, S, wave);
+    } else if (wave == 0) {
+      dc_deflate_big(Zc, E.dd, E.ee, W, n);
+    }
     __syncthreads();
     const DcPos P = dc_pos(W, n, S, q);
     const double *dk = W.dk + P.lo, *zk = W.zk + P.lo;
@@ -1289,8 +1372,8 @@ __device__ void tri_dc(const EigWs &E, double *base) {
     __syncthreads();
     if (q < n && P.t < P.s) {                       // column t of u, normalised; the eigenvalues
       const int t = P.t, K = P.K;
-      if (t < K) {
-        double nrm = 0.0, uv[16];                   // K <= 64 and L >= 4: at most 16 per lane
+      if (t < K && K <= 16 * L) {                  // at most 16 per lane: kept in registers
+        double nrm = 0.0, uv[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           const int i = sub + c * L;
@@ -1303,6 +1386,15 @@ __device__ void tri_dc(const EigWs &E, double *base) {
           const int i = sub + c * L;
           if (i < K) U[t * pw + i] = uv[c] * sc;
         }
+      } else if (t < K) {
+        double nrm = 0.0;
+        for (int i = sub; i < K; i += L) {
+          const double u = W.zh[P.lo + i] * rcp_nr(U[t * pw + i]);
+          U[t * pw + i] = u;
+          nrm = fma(u, u, nrm);
+        }
+        const double sc = 1.0 / sqrt(lsum(nrm, L));
+        for (int i = sub; i < K; i += L) U[t * pw + i] *= sc;
       }
       if (sub == 0) E.dd[P.lo + t] = t < K ? W.tau[P.lo + t] : W.D[P.lo + W.defl[P.lo + (t - K)]];
     }
@@ -1348,9 +1440,9 @@ __device__ void tri_dc(const EigWs &E, double *base) {
   }
 }
 
-// Tridiagonalise E.A and solve T: by divide and conquer into the work area at dcws when
-// given (order <= kDcMax), else by implicit QL.
-__device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed, double *dcws = nullptr) {
+// Tridiagonalise E.A and solve T: by divide and conquer in the buffers dcb when use_dc
+// (order <= kDcMax), else by implicit QL.
+__device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed, bool use_dc = false, DcBufs dcb = DcBufs{}) {
   const int n = E.n, pa = E.pa, tid = threadIdx.x, wave = tid >> 6;
   double *A = E.A, *vv = E.vv, *pp = E.pp, *ww = E.ww, *dd = E.dd, *ee = E.ee, *hv = E.hv;
   long long tph = wall_clock64();
@@ -1446,8 +1538,8 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed, double *dcws 
   }
   __syncthreads();
   if (timed && tid == 0) { const long long t = wall_clock64(); sc->ticks[0] += t - tph; tph = t; }
-  if (dcws) {
-    tri_dc(E, dcws);
+  if (use_dc) {
+    tri_dc(E, dcb);
     if (timed && tid == 0) sc->ticks[6] += wall_clock64() - tph;
     return;
   }
@@ -2074,10 +2166,23 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
     E.A[i * E.pa + j] = 0.5 * (L[int64_t(i) * ld + j] + L[int64_t(j) * ld + i]);
   }
   __syncthreads();
-  // divide and conquer where its work area fits beside the solve's, else QL
-  double *dcws = lds + eig_lds_doubles(n) + (hv_lds ? n * n + n : 0);
-  const bool dc = !big && !kp.tridiag_ql && n <= kDcMax && dcws + dc_lds_doubles(n) <= lds + kLdsDoubles;
-  tri_ql(E, sc, true, dc ? dcws : nullptr);
+  // divide and conquer where its work area fits (all in LDS up to order 64; up to 128 with
+  // the second eigenvector buffer and the merge matrices in the op's scratch after the
+  // reflectors), else QL
+  DcBufs dcb{};
+  bool dc = false;
+  if (!big && !kp.tridiag_ql) {
+    double *after = lds + eig_lds_doubles(n) + (hv_lds ? n * n + n : 0);
+    if (n <= kDcLdsMax && after + dc_lds_doubles(n) <= lds + kLdsDoubles) {
+      dcb = DcBufs{after + 2 * n * (n + 1), after, after + n * (n + 1)};
+      dc = true;
+    } else if (n <= kDcMax && after + dc_vec_doubles(n) <= lds + kLdsDoubles) {
+      double *g0 = ws + op.b + (hv_lds ? 0 : int64_t(n) * n + n);
+      dcb = DcBufs{after, g0, g0 + int64_t(n) * (n + 1)};
+      dc = true;
+    }
+  }
+  tri_ql(E, sc, true, dc, dcb);
   t0 = wall_clock64();
   order_desc(E);
   if (tid == 0) {

@@ -424,8 +424,10 @@ class Builder {
     U.rows = Box{1, 1, {slot}, {int32_t(ucols)}};
     U.cols = L.rows;
     U.ncols = n;
-    o.flags |= F_V_GLOBAL | flags;            // reflector scratch: n x n solve, then p x p solve
-    int32_t scratch = new_buf(2 * (n * n + n));
+    // scratch: reflectors (n^2 + n), then the matrix and Z of a solve too large for LDS, or the
+    // second eigenvector buffer and the merge matrices of a divide-and-conquer solve
+    o.flags |= F_V_GLOBAL | flags;
+    int32_t scratch = new_buf(3 * (n * n + n));
     int32_t id = emit(o);
     refs_.push_back({id, 1, L.buf});
     vb_[L.buf].last = std::max(vb_[L.buf].last, id);

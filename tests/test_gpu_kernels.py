@@ -81,9 +81,10 @@ def _hard_spectra(n, rng):
     yield "near_flat", np.sort(1.0 + 1e-9 * rng.standard_normal(n))[::-1]
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16, 24, 32, 40, 47, 56, 63, 64])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16, 24, 32, 40, 47, 56, 63, 64, 65, 80, 91, 100, 127, 128])
 def test_eig_divide_and_conquer_matches_ql_and_oracle(T, n):
-    """The divide-and-conquer tridiagonal solve (orders up to 64) against the QL solve and
+    """The divide-and-conquer tridiagonal solve (orders up to 64 in LDS, 65 to 128 with its
+    second eigenvector buffer and merge matrices in global scratch) against the QL solve and
     the oracle: same kept rank, orthonormal vectors, and kept subspaces that agree within
     eps ||L|| / gap at the cut (both solvers are backward stable)."""
     rng = np.random.default_rng(100 + n)
