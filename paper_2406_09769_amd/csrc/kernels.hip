@@ -49,9 +49,10 @@ __device__ __forceinline__ int32_t box_eff(const Box &b) {
   return n;
 }
 
-// compact index in [0, box_eff) -> static index in the (cap..., rest) layout
+// compact index in [0, box_eff) -> static index in the (cap..., rest) layout. With one
+// runtime dimension (outermost) the valid box is a prefix of the layout: the identity.
 __device__ __forceinline__ int32_t box_conv(const Box &b, int32_t i) {
-  if (b.nd == 0) return i;
+  if (b.nd <= 1) return i;
   int32_t r = i % b.rest;
   int32_t q = i / b.rest;
   int32_t s = 0, mult = b.rest;
@@ -1512,8 +1513,23 @@ __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed, bool use_dc =
       const int b = bh + lane;
       if (b < m) {
         const double vb = vv[b], pb = pp[b];
-#pragma unroll 4
-        for (int a = wave; a < m; a += kThreads / 64) {
+        int a = wave;
+        for (; a + 12 < m; a += 16) {                    // 4 rows: all loads before the stores
+          double va[4], pv[4], x[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            va[u] = vv[a + 4 * u];
+            pv[u] = pp[a + 4 * u];
+            x[u] = A[(j + 1 + a + 4 * u) * pa + j + 1 + b];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double val = x[u] - (va[u] * pb + pv[u] * vb - K2 * va[u] * vb);
+            A[(j + 1 + a + 4 * u) * pa + j + 1 + b] = val;
+            if (b == 0 && a + 4 * u >= 1) nxt += val * val;   // next column, below its diagonal
+          }
+        }
+        for (; a < m; a += kThreads / 64) {
           const double va = vv[a];
           double *x = A + (j + 1 + a) * pa + j + 1 + b;
           const double val = *x - (va * pb + pp[a] * vb - K2 * va * vb);
@@ -2274,7 +2290,18 @@ __device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__r
       for (int i = j + 1 + sub; i < m; i += 4) a = fma(X[i * pitch + j], X[i * pitch + t], a);
       const double w = bj * quad_sum(a);
       if (sub == 0) X[j * pitch + t] -= w * vj;
-      for (int i = j + 1 + sub; i < m; i += 4) X[i * pitch + t] = fma(-w, X[i * pitch + j], X[i * pitch + t]);
+      int i = j + 1 + sub;                           // loads of 4 rows issued before their stores
+      for (; i + 12 < m; i += 16) {
+        const double v0 = X[i * pitch + j], v1 = X[(i + 4) * pitch + j], v2 = X[(i + 8) * pitch + j],
+                     v3 = X[(i + 12) * pitch + j];
+        const double x0 = X[i * pitch + t], x1 = X[(i + 4) * pitch + t], x2 = X[(i + 8) * pitch + t],
+                     x3 = X[(i + 12) * pitch + t];
+        X[i * pitch + t] = fma(-w, v0, x0);
+        X[(i + 4) * pitch + t] = fma(-w, v1, x1);
+        X[(i + 8) * pitch + t] = fma(-w, v2, x2);
+        X[(i + 12) * pitch + t] = fma(-w, v3, x3);
+      }
+      for (; i < m; i += 4) X[i * pitch + t] = fma(-w, X[i * pitch + j], X[i * pitch + t]);
     }
     __syncthreads();
   }
@@ -2289,7 +2316,17 @@ __device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__r
       for (int i = j + 1 + sub; i < m; i += 4) a = fma(X[i * pitch + j], qc[i], a);
       const double w = bj * quad_sum(a);
       if (sub == 0) qc[j] -= w * vj;
-      for (int i = j + 1 + sub; i < m; i += 4) qc[i] = fma(-w, X[i * pitch + j], qc[i]);
+      int i = j + 1 + sub;                           // loads of 4 rows issued before their stores
+      for (; i + 12 < m; i += 16) {
+        const double v0 = X[i * pitch + j], v1 = X[(i + 4) * pitch + j], v2 = X[(i + 8) * pitch + j],
+                     v3 = X[(i + 12) * pitch + j];
+        const double q0 = qc[i], q1 = qc[i + 4], q2 = qc[i + 8], q3 = qc[i + 12];
+        qc[i] = fma(-w, v0, q0);
+        qc[i + 4] = fma(-w, v1, q1);
+        qc[i + 8] = fma(-w, v2, q2);
+        qc[i + 12] = fma(-w, v3, q3);
+      }
+      for (; i < m; i += 4) qc[i] = fma(-w, X[i * pitch + j], qc[i]);
     }
   }
   __syncthreads();
