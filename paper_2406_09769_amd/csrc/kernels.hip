@@ -523,6 +523,7 @@ __device__ double pow2_scale(double amax) {
 // LDS doubles of the two stages of a gemm_piped configuration
 constexpr int piped_stage_doubles(int MB, int NB, int KC) { return 2 * (KC * (MB + 1) + KC * (NB + 1)); }
 constexpr int kPipedTiles = piped_stage_doubles(32, 128, 32);   // the largest configuration below
+constexpr int64_t kDirectFma = 65536;  // products up to this many multiply-adds skip the pipeline
 static_assert(2 * split_stage_words(64, 64, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
 static_assert(2 * split_stage_words(32, 128, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
 static_assert(2 * split_stage_words(16, 256, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
@@ -572,6 +573,34 @@ __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double
       if (M <= 16) gemm_split<16, 256, 16, 1, 4, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
       else if (M <= 32) gemm_split<32, 128, 16, 2, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
       else gemm_split<64, 64, 16, 2, 2, 2>(op, A, B, C, lds, M, N, K, kA, kB, rA, cB, rC, cC, sa, sb);
+    }
+    return true;
+  }
+  // a small product (at most kDirectFma multiply-adds, both operands within the stage area):
+  // both operands staged in LDS with one round trip, then every output from LDS on the VALU
+  // (no k-chunk pipeline, no matrix-core blocks mostly of padding at these sizes)
+  if (int64_t(M) * N * K <= kDirectFma && M * K + K * N <= kPipedTiles) {
+    double *As = lds, *Bs = lds + M * K;                 // A[m][k], B[k][n]
+    for (int e = tid; e < M * K; e += kThreads) {
+      const int m = e / K, k = e - m * K;
+      As[e] = A[int64_t(rA[m]) + kA[k]];
+    }
+    for (int e = tid; e < K * N; e += kThreads) {
+      const int k = e / N, n = e - k * N;
+      Bs[e] = B[int64_t(cB[n]) + kB[k]];
+    }
+    __syncthreads();
+    for (int e = tid; e < M * N; e += kThreads) {
+      const int m = e / N, n = e - m * N;
+      const double *a = As + m * K, *b = Bs + n;
+      double s0 = 0.0, s1 = 0.0;
+      int k = 0;
+      for (; k + 1 < K; k += 2) {
+        s0 = fma(a[k], b[k * N], s0);
+        s1 = fma(a[k + 1], b[(k + 1) * N], s1);
+      }
+      if (k < K) s0 = fma(a[k], b[k * N], s0);
+      C[int64_t(rC[m]) + cC[n]] = s0 + s1;
     }
     return true;
   }
@@ -948,10 +977,10 @@ __device__ void tri_reduce_wave(const EigWs &E) {
 // ---------------------------------------------------------------- divide and conquer
 //
 // Tridiagonal eigensolve by divide and conquer for orders up to kDcMax, used in place of
-// QL where its work area fits LDS. Every off-diagonal e_i tears T into
-// diag(T1, T2) + rho v v^T (rho = |e_i|, v = e_i + sign(e_i) e_{i+1}), so the leaves are
-// the 1 x 1 blocks d_i - |e_{i-1}| - |e_i|; blocks are merged bottom-up, pairs of width
-// S/2 into width S. A merge of children with eigenpairs (D1, Q1), (D2, Q2) solves
+// QL. Every off-diagonal e_i tears T into diag(T1, T2) + rho v v^T (rho = |e_i|,
+// v = e_i + sign(e_i) e_{i+1}), so the leaves are the 1 x 1 blocks d_i - |e_{i-1}| - |e_i|;
+// blocks are merged bottom-up, pairs of width S/2 into width S (the first level, 2 x 2
+// blocks, in closed form). A merge of children with eigenpairs (D1, Q1), (D2, Q2) solves
 // D + rho z z^T with z = (last row of Q1, sign * first row of Q2):
 //  * deflation: components with rho |z_i| <= tol keep (D_i, column i); pairs of close
 //    D (|(D_j - D_i) c s| <= tol after the rotation that moves z_i into z_j) are rotated
@@ -1339,8 +1368,31 @@ __device__ void tri_dc(const EigWs &E, const DcBufs &bufs) {
   for (int i = tid; i < n; i += kThreads)           // the tears: leaves d_i - |e_i-1| - |e_i|
     E.dd[i] -= (i > 0 ? fabs(E.ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(E.ee[i]) : 0.0);
   __syncthreads();
+  // the first level in closed form: block [2p, 2p+1] = [[a, b], [b, c]] (its inner tear
+  // undone) by one Jacobi rotation, eigenvectors (cs, -sn) and (sn, cs)
+  for (int p = tid; 2 * p + 1 < n; p += kThreads) {
+    const int i = 2 * p;
+    const double b = E.ee[i], r = fabs(b);
+    const double a = E.dd[i] + r, c = E.dd[i + 1] + r;
+    double cs = 1.0, sn = 0.0, l1 = a, l2 = c;
+    if (b != 0.0) {
+      const double th = (c - a) / (2.0 * b);
+      const double t = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+      cs = 1.0 / sqrt(fma(t, t, 1.0));
+      sn = t * cs;
+      l1 = a - t * b;
+      l2 = c + t * b;
+    }
+    E.dd[i] = l1;
+    E.dd[i + 1] = l2;
+    Za[i * zp + i] = cs;
+    Za[i * zp + i + 1] = -sn;
+    Za[(i + 1) * zp + i] = sn;
+    Za[(i + 1) * zp + i + 1] = cs;
+  }
+  __syncthreads();
   double *Zc = Za, *Zn = Zb;
-  for (int S = 2; S / 2 < n; S *= 2) {
+  for (int S = 4; S / 2 < n; S *= 2) {
     if (S <= 64) {
       if (64 * wave < n) dc_deflate(Zc, E.dd, E.ee, W, n, S, wave);
     } else if (wave == 0) {
