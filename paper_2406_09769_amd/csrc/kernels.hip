@@ -638,6 +638,11 @@ constexpr int kDppRowHalfMirror = 0x141;
 constexpr int kDppRowMirror = 0x140;
 constexpr int kDppRowBcast15 = 0x142;   // lane 15 of each row to the next row
 constexpr int kDppRowBcast31 = 0x143;   // lane 31 to rows 2 and 3
+__device__ __forceinline__ double lane0(double v) {     // lane 0's value, as a uniform scalar
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 0);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 0);
+  return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double lane63(double v) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
@@ -921,7 +926,7 @@ __device__ void tri_reduce_wave(const EigWs &E) {
     double *row = A + (j + 1 + lane) * pa + j + 1;       // lane's row of the trailing block
     const double x = act ? row[-1] : 0.0;                 // column j below the diagonal
     const double nrm2 = wave_sum(x * x);
-    const double x0 = __shfl(x, 0, 64);
+    const double x0 = lane0(x);
     if (nrm2 == 0.0) {                                    // column already reduced
       if (lane == 0) { dd[j] = A[j * pa + j]; ee[j] = 0.0; hv[int64_t(n) * n + j] = 0.0; }
       continue;
@@ -1027,7 +1032,12 @@ __device__ DcWs dc_ws(const DcBufs &b, int n) {
 
 // max over aligned groups of g lanes (g a power of two <= 64)
 __device__ __forceinline__ double group_max(double v, int g) {
-  for (int off = 1; off < g; off <<= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if (g >= 2) v = fmax(v, dpp_f64<kDppQuadXor1>(v));       // within rows of 16 on DPP
+  if (g >= 4) v = fmax(v, dpp_f64<kDppQuadXor2>(v));
+  if (g >= 8) v = fmax(v, dpp_f64<kDppRowHalfMirror>(v));
+  if (g >= 16) v = fmax(v, dpp_f64<kDppRowMirror>(v));
+  if (g >= 32) v = fmax(v, __shfl_xor(v, 16, 64));          // across rows: two moves
+  if (g >= 64) v = fmax(v, __shfl_xor(v, 32, 64));
   return v;
 }
 

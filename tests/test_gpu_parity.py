@@ -188,6 +188,25 @@ def test_w3_full_size_against_golden(T):
         del h
 
 
+def test_w3_chi32_against_golden(T):
+    """8x8x8 open cubic lattice at chi 32 (right environments of up to 2.1 GB, a 103 GB
+    workspace on the device) against the oracle value stored by make_golden.py (the oracle
+    keeps every 8th environment and recomputes the rest, a memory schedule pinned
+    bit-identical to keeping them all). Same 1e-10 bound as at chi 16."""
+    path = os.path.join(HERE, "golden", "w3_chi32_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored chi 32 oracle value (make_golden.py w3chi32 writes it in about 3 hours)")
+    for g in json.load(open(path))["rows"]:
+        net = inputs.ising_3d(8, 8, 8, g["beta"])
+        h = T.create_network(net)
+        r = T.tn_contract_approx(h, net.slices, g["chi"], g["env"])
+        d = abs(r.log_abs - g["log_abs"]) / net.n_sites
+        print(f"W3 beta={g['beta']} chi={g['chi']}: gpu {r.log_abs!r} oracle {g['log_abs']!r} diff/N {d:.3e}, "
+              f"{r.seconds:.2f} s", flush=True)
+        assert r.sign == g["sign"] and d <= TOL
+        del h
+
+
 def test_chip_wide_network_replays_its_graph(T):
     """A network with chip-wide ops runs from a captured HIP graph: repeated calls replay it
     (identical results), a call with other launch parameters captures anew, and going back
