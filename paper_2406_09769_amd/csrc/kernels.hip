@@ -528,6 +528,42 @@ static_assert(2 * split_stage_words(64, 64, 16) <= 4 * (kPipedTiles - 8), "split
 static_assert(2 * split_stage_words(32, 128, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
 static_assert(2 * split_stage_words(16, 256, 16) <= 4 * (kPipedTiles - 8), "split stages fit");
 
+// Outputs of a small product from LDS: a thread per (R rows, column) item; rows m0..m0+R-1
+// of As (k-major, pitch Mp) against column n of Bs, R (or, for R < 4, 2R) independent sums.
+template <int R>
+__device__ __forceinline__ void gemm_direct_rows(const double *As, const double *Bs, double *__restrict__ C, int M,
+                                                 int Mp, int N, int K, const int32_t *rC, const int32_t *cC) {
+  constexpr int P = R < 4 ? 2 : 1;                       // partial sums per row
+  const int items = (Mp / R) * N;
+  for (int e = threadIdx.x; e < items; e += kThreads) {
+    const int mb = e / N, n = e - mb * N, m0 = mb * R;
+    const double *a = As + m0, *b = Bs + n;
+    double s[P][R];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[p][r] = 0.0;
+    int k = 0;
+    for (; k + P <= K; k += P) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const double bk = b[(k + p) * N];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[p][r] = fma(a[(k + p) * Mp + r], bk, s[p][r]);
+      }
+    }
+    if (k < K) {
+      const double bk = b[k * N];
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[0][r] = fma(a[k * Mp + r], bk, s[0][r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (m0 + r < M) C[int64_t(rC[m0 + r]) + cC[n]] = P == 2 ? s[0][r] + s[P - 1][r] : s[0][r];
+    }
+  }
+}
+
 // One GEMM op. Returns false when its offsets do not fit the LDS cache (the caller
 // then runs gemm_tiles_k).
 __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double *__restrict__ B,
@@ -578,31 +614,28 @@ __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double
   }
   // a small product (at most kDirectFma multiply-adds, both operands within the stage area):
   // both operands staged in LDS with one round trip, then every output from LDS on the VALU
-  // (no k-chunk pipeline, no matrix-core blocks mostly of padding at these sizes)
-  if (int64_t(M) * N * K <= kDirectFma && M * K + K * N <= kPipedTiles) {
-    double *As = lds, *Bs = lds + M * K;                 // A[m][k], B[k][n]
-    for (int e = tid; e < M * K; e += kThreads) {
-      const int m = e / K, k = e - m * K;
-      As[e] = A[int64_t(rA[m]) + kA[k]];
-    }
-    for (int e = tid; e < K * N; e += kThreads) {
-      const int k = e / N, n = e - k * N;
-      Bs[e] = B[int64_t(cB[n]) + kB[k]];
-    }
-    __syncthreads();
-    for (int e = tid; e < M * N; e += kThreads) {
-      const int m = e / N, n = e - m * N;
-      const double *a = As + m * K, *b = Bs + n;
-      double s0 = 0.0, s1 = 0.0;
-      int k = 0;
-      for (; k + 1 < K; k += 2) {
-        s0 = fma(a[k], b[k * N], s0);
-        s1 = fma(a[k + 1], b[(k + 1) * N], s1);
+  // (no k-chunk pipeline, no matrix-core blocks mostly of padding at these sizes). A thread
+  // takes R rows of one output column, so each load of B serves R multiply-adds and the R
+  // values of A (k-major, rows padded to a multiple of R) are one read shared by the wave.
+  if (int64_t(M) * N * K <= kDirectFma) {
+    const int R = M >= 4 ? 4 : (M >= 2 ? 2 : 1);
+    const int Mp = (M + R - 1) / R * R;
+    if (Mp * K + K * N <= kPipedTiles) {
+      double *As = lds, *Bs = lds + Mp * K;              // As[k][m] (pitch Mp), Bs[k][n]
+      for (int e = tid; e < M * K; e += kThreads) {
+        const int m = e / K, k = e - m * K;
+        As[k * Mp + m] = A[int64_t(rA[m]) + kA[k]];
       }
-      if (k < K) s0 = fma(a[k], b[k * N], s0);
-      C[int64_t(rC[m]) + cC[n]] = s0 + s1;
+      for (int e = tid; e < K * N; e += kThreads) {
+        const int k = e / N, n = e - k * N;
+        Bs[e] = B[int64_t(cB[n]) + kB[k]];
+      }
+      __syncthreads();
+      if (R == 4) gemm_direct_rows<4>(As, Bs, C, M, Mp, N, K, rC, cC);
+      else if (R == 2) gemm_direct_rows<2>(As, Bs, C, M, Mp, N, K, rC, cC);
+      else gemm_direct_rows<1>(As, Bs, C, M, Mp, N, K, rC, cC);
+      return true;
     }
-    return true;
   }
   // block configuration: the option's choice for this row class, else 16x512 / 32x128 / 64x64
   const int cls = M <= 16 ? 0 : (M <= 32 ? 1 : 2);
@@ -984,8 +1017,8 @@ __device__ void tri_reduce_wave(const EigWs &E) {
 // Tridiagonal eigensolve by divide and conquer for orders up to kDcMax, used in place of
 // QL. Every off-diagonal e_i tears T into diag(T1, T2) + rho v v^T (rho = |e_i|,
 // v = e_i + sign(e_i) e_{i+1}), so the leaves are the 1 x 1 blocks d_i - |e_{i-1}| - |e_i|;
-// blocks are merged bottom-up, pairs of width S/2 into width S (the first level, 2 x 2
-// blocks, in closed form). A merge of children with eigenpairs (D1, Q1), (D2, Q2) solves
+// blocks are merged bottom-up, pairs of width S/2 into width S (the first two levels, the
+// 4 x 4 blocks, directly by Jacobi rotations). A merge of children with eigenpairs (D1, Q1), (D2, Q2) solves
 // D + rho z z^T with z = (last row of Q1, sign * first row of Q2):
 //  * deflation: components with rho |z_i| <= tol keep (D_i, column i); pairs of close
 //    D (|(D_j - D_i) c s| <= tol after the rotation that moves z_i into z_j) are rotated
@@ -1343,6 +1376,67 @@ __device__ __noinline__ void dc_deflate_big(double *Z, const double *dd, const d
   for (int t = lane; t < K; t += 64) { W.dk[t] = W.D[W.kept[t]]; W.zk[t] = W.z[W.kept[t]]; }
 }
 
+// 1/sqrt(x) from the hardware estimate and two Newton steps (x well inside the normal range)
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// Jacobi rotation of the symmetric 4 x 4 a (eigenvectors v) that zeroes a[I][J]: with
+// d = a_JJ - a_II and t = tan of the angle, the smaller root of t^2 + (d / a_IJ) t - 1 = 0,
+// t = sign(d) 2 a_IJ / (|d| + sqrt(d^2 + 4 a_IJ^2)), formed after scaling d and 2 a_IJ by the
+// larger of the two; then a_II -= t a_IJ, a_JJ += t a_IJ. Entries at or below
+// eps (|a_II| + |a_JJ|) / 2 are dropped instead (t = 0).
+struct JacRot {
+  double t, cs, sn;
+  bool rot;
+};
+template <int I, int J>
+__device__ __forceinline__ JacRot jac4_angle(const double (&a)[4][4]) {
+  constexpr double kEps = 2.220446049250313e-16;
+  JacRot R;
+  const double aij = a[I][J];
+  R.rot = fabs(aij) > 0.5 * kEps * (fabs(a[I][I]) + fabs(a[J][J]));
+  const double d = a[J][J] - a[I][I], g = 2.0 * aij;
+  const double rm = rcp_nr(R.rot ? fmax(fabs(d), fabs(g)) : 1.0);
+  const double dn = d * rm, gn = g * rm;
+  const double h = fma(dn, dn, gn * gn);                 // in [1, 2]
+  const double t = (d >= 0.0 ? gn : -gn) * rcp_nr(fabs(dn) + h * rsq_nr(h));
+  R.t = R.rot ? t : 0.0;
+  R.cs = R.rot ? rsq_nr(fma(t, t, 1.0)) : 1.0;
+  R.sn = R.t * R.cs;
+  return R;
+}
+template <int I, int J>
+__device__ __forceinline__ void jac4_apply(double (&a)[4][4], double (&v)[4][4], const JacRot &R) {
+  const double aij = a[I][J];
+  a[I][I] -= R.t * aij;
+  a[J][J] += R.t * aij;
+  a[I][J] = 0.0;
+  a[J][I] = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (r != I && r != J) {
+      const double x = a[r][I], y = a[r][J];
+      a[r][I] = a[I][r] = R.cs * x - R.sn * y;
+      a[r][J] = a[J][r] = R.sn * x + R.cs * y;
+    }
+    const double x = v[r][I], y = v[r][J];
+    v[r][I] = R.cs * x - R.sn * y;
+    v[r][J] = R.sn * x + R.cs * y;
+  }
+}
+// One round of a cyclic sweep: the planes (I, J) and (K, L) are disjoint, so neither angle
+// depends on the other rotation and both are formed together. True if either rotated.
+template <int I, int J, int K, int L>
+__device__ __forceinline__ bool jac4_round(double (&a)[4][4], double (&v)[4][4]) {
+  const JacRot r1 = jac4_angle<I, J>(a), r2 = jac4_angle<K, L>(a);
+  jac4_apply<I, J>(a, v, r1);
+  jac4_apply<K, L>(a, v, r2);
+  return r1.rot || r2.rot;
+}
+
 // The merge and the position within it that quad q (= index q of the level) stands for.
 struct DcPos {
   int lo, t, s, K;
@@ -1378,31 +1472,46 @@ __device__ void tri_dc(const EigWs &E, const DcBufs &bufs) {
   for (int i = tid; i < n; i += kThreads)           // the tears: leaves d_i - |e_i-1| - |e_i|
     E.dd[i] -= (i > 0 ? fabs(E.ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(E.ee[i]) : 0.0);
   __syncthreads();
-  // the first level in closed form: block [2p, 2p+1] = [[a, b], [b, c]] (its inner tear
-  // undone) by one Jacobi rotation, eigenvectors (cs, -sn) and (sn, cs)
-  for (int p = tid; 2 * p + 1 < n; p += kThreads) {
-    const int i = 2 * p;
-    const double b = E.ee[i], r = fabs(b);
-    const double a = E.dd[i] + r, c = E.dd[i + 1] + r;
-    double cs = 1.0, sn = 0.0, l1 = a, l2 = c;
-    if (b != 0.0) {
-      const double th = (c - a) / (2.0 * b);
-      const double t = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-      cs = 1.0 / sqrt(fma(t, t, 1.0));
-      sn = t * cs;
-      l1 = a - t * b;
-      l2 = c + t * b;
+  // the first two levels directly: block [4p, 4p + 4) (its inner tears undone) by cyclic
+  // Jacobi in one lane, its eigenvectors into the block's columns of Z (jac4_round)
+  for (int p = tid; 4 * p < n; p += kThreads) {
+    const int i0 = 4 * p, s = n - i0 < 4 ? n - i0 : 4;
+    double a[4][4], v[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { a[r][c] = 0.0; v[r][c] = r == c ? 1.0 : 0.0; }
+      if (r < s) a[r][r] = E.dd[i0 + r];
     }
-    E.dd[i] = l1;
-    E.dd[i + 1] = l2;
-    Za[i * zp + i] = cs;
-    Za[i * zp + i + 1] = -sn;
-    Za[(i + 1) * zp + i] = sn;
-    Za[(i + 1) * zp + i + 1] = cs;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      if (r + 1 < s) {
+        const double b = E.ee[i0 + r], rb = fabs(b);
+        a[r][r] += rb;
+        a[r + 1][r + 1] += rb;
+        a[r][r + 1] = b;
+        a[r + 1][r] = b;
+      }
+    }
+    for (int sweep = 0; sweep < 16; ++sweep) {
+      bool rotated = jac4_round<0, 1, 2, 3>(a, v);
+      rotated |= jac4_round<0, 2, 1, 3>(a, v);
+      rotated |= jac4_round<0, 3, 1, 2>(a, v);
+      if (!rotated) break;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c < s) {
+        E.dd[i0 + c] = a[c][c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (r < s) Za[(i0 + c) * zp + i0 + r] = v[r][c];
+      }
+    }
   }
   __syncthreads();
   double *Zc = Za, *Zn = Zb;
-  for (int S = 4; S / 2 < n; S *= 2) {
+  for (int S = 8; S / 2 < n; S *= 2) {
     if (S <= 64) {
       if (64 * wave < n) dc_deflate(Zc, E.dd, E.ee, W, n, S, wave);
     } else if (wave == 0) {
