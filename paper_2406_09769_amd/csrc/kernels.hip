@@ -2400,19 +2400,73 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
 //
 // C (m x c valid, read through the op's row and column maps) = Q R by Householder
 // reflectors, one workgroup. C sits in LDS (odd pitch); quad t of the workgroup (4 lanes of
-// one wave) owns column t (c <= 64). Column j: quad j forms the reflector of rows j..m-1
-// (beta = 0 for a zero column), barrier, the quads of the later columns apply it, barrier.
-// Q's kk = min(m, c) columns are then formed as H_0 ... H_t e_t by quad t with no barrier
-// (the reflectors are read only). Q is written [q][rows], R [q][cols] (zero below the
-// diagonal), and kk to the op's slot.
+// one wave) owns column t (c <= 64). Column j: the quads of the later columns apply
+// reflector j, and quad j+1, as soon as its own column is updated, forms reflector j+1 of
+// rows j+1..m-1 (beta = 0 for a zero column); one barrier per column. Q's kk = min(m, c)
+// columns are then formed as H_0 ... H_t e_t by quad t with no barrier (the reflectors are
+// read only). Sums over a column run 4 rows per lane at a time into 4 partial sums, so the
+// loads of a chunk are in flight together. Q is written [q][rows], R [q][cols] (zero below
+// the diagonal), and kk to the op's slot.
+// sum over rows i = i0, i0 + 4, ... < m of x[i * px] y[i * py], 4 rows at a time into 4
+// partial sums
+__device__ __forceinline__ double quad_col_dot(const double *x, int px, const double *y, int py, int i0, int m) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = i0;
+  for (; i + 28 < m; i += 32) {                     // 8 rows: 16 loads in flight
+    double xv[8], yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) { xv[u] = x[(i + 4 * u) * px]; yv[u] = y[(i + 4 * u) * py]; }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u & 3] = fma(xv[u], yv[u], a[u & 3]);
+  }
+  for (; i + 12 < m; i += 16) {
+    double xv[4], yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { xv[u] = x[(i + 4 * u) * px]; yv[u] = y[(i + 4 * u) * py]; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = fma(xv[u], yv[u], a[u]);
+  }
+  for (; i < m; i += 4) a[0] = fma(x[i * px], y[i * py], a[0]);
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// Reflector of column j of X (rows j..m-1), by the 4 lanes of one quad: H_j = I - beta v v^T
+// with v = (x_j - alpha, x_j+1, ...) maps the column to alpha e_j.
+__device__ __forceinline__ void qr_reflector(const double *X, int pitch, int m, int j, int sub, double *vdiag,
+                                             double *bet, double *rdiag) {
+  const double *col = X + j;
+  const double tail = quad_sum(quad_col_dot(col, pitch, col, pitch, j + 1 + sub, m));
+  const double x0 = X[j * pitch + j], nrm2 = fma(x0, x0, tail);
+  if (sub == 0) {
+    if (tail == 0.0) {                               // nothing below the diagonal: H_j = I
+      bet[j] = 0.0;
+      vdiag[j] = 0.0;
+      rdiag[j] = x0;
+    } else {
+      const double alpha = -copysign(sqrt(nrm2), x0);
+      bet[j] = 1.0 / (nrm2 - x0 * alpha);            // 2 / (v^T v)
+      vdiag[j] = x0 - alpha;
+      rdiag[j] = alpha;
+    }
+  }
+}
+
+constexpr int kQrNb = 8;                            // reflectors per compact-WY block of Q
+static_assert(kQrMaxRows * (kQrMaxCols | 1) + kQrMaxCols * (kQrMaxRows | 1) + 3 * kQrMaxCols +
+                  (kQrMaxRows + kQrMaxCols) * 3 / 2 + 2 * kQrMaxCols * kQrNb <= kLdsDoubles,
+              "the QR of the largest matrix fits LDS");
+static_assert(kQrMaxCols % kQrNb == 0 && (kQrMaxCols / kQrNb) * kQrNb <= kThreads, "one lane per row of every T");
 __device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__restrict__ tab, NetScalars *sc,
                       double *lds) {
   const int m = box_eff(op.bm), c = box_eff(op.bnb), kk = m < c ? m : c;
   const int tid = threadIdx.x, sub = tid & 3, t = tid >> 2;
-  const int pitch = c | 1;
+  // odd pitches: the quads of a wave read one row of X, or one row index of their columns
+  // of Q, at addresses that spread over the LDS banks (a pitch of m = 128 doubles would put
+  // every quad of the wave on the same banks)
+  const int pitch = c | 1, mq = m | 1;
   double *X = lds;                                   // m x pitch
-  double *Qb = X + m * pitch;                        // kk x m: column t of Q at Qb[t*m + i]
-  double *vdiag = Qb + kk * m, *bet = vdiag + kQrMaxCols, *rdiag = bet + kQrMaxCols;
+  double *Qb = X + m * pitch;                        // kk x mq: column t of Q at Qb[t*mq + i]
+  double *vdiag = Qb + kk * mq, *bet = vdiag + kQrMaxCols, *rdiag = bet + kQrMaxCols;
   // offsets resolved once: C's row and column offsets, and where each valid row of Q and
   // column of R is stored (the gathers then need one load per element)
   int64_t *roff = reinterpret_cast<int64_t *>(rdiag + kQrMaxCols), *coff = roff + kQrMaxRows;
@@ -2434,70 +2488,159 @@ __device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__r
     X[i * pitch + j] = Cg[roff[i] + coff[j]];
   }
   __syncthreads();
+  if (t == 0 && kk > 0) qr_reflector(X, pitch, m, 0, sub, vdiag, bet, rdiag);
+  __syncthreads();
   for (int j = 0; j < kk; ++j) {
-    if (t == j) {                                    // the reflector of column j
-      double s = 0.0;
-      for (int i = j + 1 + sub; i < m; i += 4) s = fma(X[i * pitch + j], X[i * pitch + j], s);
-      const double x0 = X[j * pitch + j];
-      const double tail = quad_sum(s), nrm2 = fma(x0, x0, tail);
-      if (sub == 0) {
-        if (tail == 0.0) {                           // nothing below the diagonal: H_j = I
-          bet[j] = 0.0;
-          vdiag[j] = 0.0;
-          rdiag[j] = x0;
-        } else {
-          const double alpha = -copysign(sqrt(nrm2), x0);
-          bet[j] = 1.0 / (nrm2 - x0 * alpha);        // 2 / (v^T v)
-          vdiag[j] = x0 - alpha;
-          rdiag[j] = alpha;
-        }
-      }
-    }
-    __syncthreads();
     const double bj = bet[j];
     if (t > j && t < c && bj != 0.0) {               // apply H_j to column t
       const double vj = vdiag[j];
-      double a = sub == 0 ? vj * X[j * pitch + t] : 0.0;
-      for (int i = j + 1 + sub; i < m; i += 4) a = fma(X[i * pitch + j], X[i * pitch + t], a);
-      const double w = bj * quad_sum(a);
+      const double a = quad_sum((sub == 0 ? vj * X[j * pitch + t] : 0.0) +
+                                quad_col_dot(X + j, pitch, X + t, pitch, j + 1 + sub, m));
+      const double w = bj * a;
       if (sub == 0) X[j * pitch + t] -= w * vj;
-      int i = j + 1 + sub;                           // loads of 4 rows issued before their stores
-      for (; i + 12 < m; i += 16) {
-        const double v0 = X[i * pitch + j], v1 = X[(i + 4) * pitch + j], v2 = X[(i + 8) * pitch + j],
-                     v3 = X[(i + 12) * pitch + j];
-        const double x0 = X[i * pitch + t], x1 = X[(i + 4) * pitch + t], x2 = X[(i + 8) * pitch + t],
-                     x3 = X[(i + 12) * pitch + t];
-        X[i * pitch + t] = fma(-w, v0, x0);
-        X[(i + 4) * pitch + t] = fma(-w, v1, x1);
-        X[(i + 8) * pitch + t] = fma(-w, v2, x2);
-        X[(i + 12) * pitch + t] = fma(-w, v3, x3);
+      int i = j + 1 + sub;                           // loads of 8 rows issued before their stores
+      for (; i + 28 < m; i += 32) {
+        double vb[8], xb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) { vb[u] = X[(i + 4 * u) * pitch + j]; xb[u] = X[(i + 4 * u) * pitch + t]; }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) X[(i + 4 * u) * pitch + t] = fma(-w, vb[u], xb[u]);
       }
       for (; i < m; i += 4) X[i * pitch + t] = fma(-w, X[i * pitch + j], X[i * pitch + t]);
     }
+    if (t == j + 1 && j + 1 < kk) {                  // column j+1 is final: its reflector
+      __threadfence_block();                         // the quad's stores above, before its loads
+      qr_reflector(X, pitch, m, j + 1, sub, vdiag, bet, rdiag);
+    }
     __syncthreads();
   }
-  if (t < kk) {                                      // Q e_t = H_0 ... H_t e_t
-    double *qc = Qb + t * m;
-    for (int i = sub; i < m; i += 4) qc[i] = i == t ? 1.0 : 0.0;
-    for (int j = t; j >= 0; --j) {
-      const double bj = bet[j];
-      if (bj == 0.0) continue;                       // the same j and beta in every lane of the quad
-      const double vj = vdiag[j];
-      double a = sub == 0 ? vj * qc[j] : 0.0;
-      for (int i = j + 1 + sub; i < m; i += 4) a = fma(X[i * pitch + j], qc[i], a);
-      const double w = bj * quad_sum(a);
-      if (sub == 0) qc[j] -= w * vj;
-      int i = j + 1 + sub;                           // loads of 4 rows issued before their stores
-      for (; i + 12 < m; i += 16) {
-        const double v0 = X[i * pitch + j], v1 = X[(i + 4) * pitch + j], v2 = X[(i + 8) * pitch + j],
-                     v3 = X[(i + 12) * pitch + j];
-        const double q0 = qc[i], q1 = qc[i + 4], q2 = qc[i + 8], q3 = qc[i + 12];
-        qc[i] = fma(-w, v0, q0);
-        qc[i + 4] = fma(-w, v1, q1);
-        qc[i + 8] = fma(-w, v2, q2);
-        qc[i + 12] = fma(-w, v3, q3);
+  // Q's columns from blocks of kQrNb reflectors in compact WY form: H_j0 ... H_j0+nb-1 =
+  // I - V T V^T with T upper triangular, T_pp = beta_p and T_lp = -beta_p sum_q T_lq G_qp
+  // (G = V^T V of the block). Quads take the blocks' Gram entries, one lane per row of a T
+  // builds it; then quad t forms Q e_t = H_0 ... H_t e_t by the blocks that touch it, last
+  // block first, with no barrier: p = V^T q, p <- T p, q -= V p.
+  const int nblk = (kk + kQrNb - 1) / kQrNb;
+  double *Gb = reinterpret_cast<double *>(rpos + kQrMaxCols), *Tb = Gb + kQrMaxCols * kQrNb;
+  constexpr int kPairs = kQrNb * (kQrNb - 1) / 2;
+  for (int task = t; task < nblk * kPairs; task += kThreads / 4) {
+    const int blk = task / kPairs;
+    int pr = 0, rr = task % kPairs;                  // pair (pr, qr), pr < qr, of the block
+    while (rr >= kQrNb - 1 - pr) { rr -= kQrNb - 1 - pr; ++pr; }
+    const int qr = pr + 1 + rr, jp = blk * kQrNb + pr, jq = blk * kQrNb + qr;
+    double g = 0.0;
+    if (jq < kk)                                     // rows >= jq (v_jq is zero above its diagonal)
+      g = quad_sum((sub == 0 ? X[jq * pitch + jp] * vdiag[jq] : 0.0) +
+                   quad_col_dot(X + jp, pitch, X + jq, pitch, jq + 1 + sub, m));
+    if (sub == 0) Gb[(blk * kQrNb + pr) * kQrNb + qr] = g;
+  }
+  __syncthreads();
+  if (tid < nblk * kQrNb) {
+    const int blk = tid / kQrNb, l = tid % kQrNb, j0 = blk * kQrNb;
+    double trow[kQrNb];
+#pragma unroll
+    for (int p = 0; p < kQrNb; ++p) {
+      double v = 0.0;
+      if (j0 + p < kk) {
+        const double bp = bet[j0 + p];
+        if (p == l) {
+          v = bp;
+        } else if (l < p) {
+          double s = 0.0;
+#pragma unroll
+          for (int q = 0; q < p; ++q)
+            if (q >= l) s = fma(trow[q], Gb[(j0 + q) * kQrNb + p], s);
+          v = -bp * s;
+        }
       }
-      for (; i < m; i += 4) qc[i] = fma(-w, X[i * pitch + j], qc[i]);
+      trow[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < kQrNb; ++p) Tb[(j0 + l) * kQrNb + p] = trow[p];
+  }
+  __syncthreads();
+  if (t < kk) {
+    double *qc = Qb + t * mq;
+    for (int i = sub; i < m; i += 4) qc[i] = i == t ? 1.0 : 0.0;
+    for (int blk = t / kQrNb; blk >= 0; --blk) {
+      const int j0 = blk * kQrNb, nb = kk - j0 < kQrNb ? kk - j0 : kQrNb;
+      // q's rows above j0 are still zero; rows j0 .. j0+7 meet the triangle of V (masked),
+      // the rows below read V's row straight from X (all of it in a full block)
+      double pv[kQrNb], w[kQrNb];
+#pragma unroll
+      for (int p = 0; p < kQrNb; ++p) pv[p] = 0.0;
+      const int tri = j0 + kQrNb < m ? j0 + kQrNb : m;
+      for (int i = j0 + sub; i < tri; i += 4) {
+        const double qi = qc[i];
+#pragma unroll
+        for (int p = 0; p < kQrNb; ++p) {
+          const double vip = p < nb && i >= j0 + p ? (i == j0 + p ? vdiag[j0 + p] : X[i * pitch + j0 + p]) : 0.0;
+          pv[p] = fma(vip, qi, pv[p]);
+        }
+      }
+      if (nb == kQrNb) {
+        int i = tri + ((j0 + sub - tri) & 3);
+        for (; i + 4 < m; i += 8) {                  // two rows: their loads in flight together
+          const double q0 = qc[i], q1 = qc[i + 4];
+          const double *x0 = X + i * pitch + j0, *x1 = x0 + 4 * pitch;
+          double r0[kQrNb], r1[kQrNb];
+#pragma unroll
+          for (int p = 0; p < kQrNb; ++p) { r0[p] = x0[p]; r1[p] = x1[p]; }
+#pragma unroll
+          for (int p = 0; p < kQrNb; ++p) pv[p] = fma(r1[p], q1, fma(r0[p], q0, pv[p]));
+        }
+        if (i < m) {
+          const double qi = qc[i];
+          const double *xr = X + i * pitch + j0;
+#pragma unroll
+          for (int p = 0; p < kQrNb; ++p) pv[p] = fma(xr[p], qi, pv[p]);
+        }
+      } else {
+        for (int i = tri + ((j0 + sub - tri) & 3); i < m; i += 4) {
+          const double qi = qc[i];
+          const double *xr = X + i * pitch + j0;
+#pragma unroll
+          for (int p = 0; p < kQrNb; ++p) pv[p] = fma(p < nb ? xr[p] : 0.0, qi, pv[p]);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < kQrNb; ++p) pv[p] = quad_sum(pv[p]);
+#pragma unroll
+      for (int l = 0; l < kQrNb; ++l) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < kQrNb; ++p)
+          if (p >= l) s = fma(Tb[(j0 + l) * kQrNb + p], pv[p], s);
+        w[l] = s;
+      }
+      for (int i = j0 + sub; i < tri; i += 4) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < kQrNb; ++p) {
+          const double vip = p < nb && i >= j0 + p ? (i == j0 + p ? vdiag[j0 + p] : X[i * pitch + j0 + p]) : 0.0;
+          s = fma(vip, w[p], s);
+        }
+        qc[i] -= s;
+      }
+      int i = tri + ((j0 + sub - tri) & 3);        // w[p] = 0 for p >= nb
+      for (; i + 4 < m; i += 8) {                    // two rows: their loads in flight together
+        const double *x0 = X + i * pitch + j0, *x1 = x0 + 4 * pitch;
+        double r0[kQrNb], r1[kQrNb];
+#pragma unroll
+        for (int p = 0; p < kQrNb; ++p) { r0[p] = p < nb ? x0[p] : 0.0; r1[p] = p < nb ? x1[p] : 0.0; }
+        const double q0 = qc[i], q1 = qc[i + 4];
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int p = 0; p < kQrNb; ++p) { s0 = fma(r0[p], w[p], s0); s1 = fma(r1[p], w[p], s1); }
+        qc[i] = q0 - s0;
+        qc[i + 4] = q1 - s1;
+      }
+      if (i < m) {
+        const double *xr = X + i * pitch + j0;
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < kQrNb; ++p) s = fma(p < nb ? xr[p] : 0.0, w[p], s);
+        qc[i] -= s;
+      }
     }
   }
   __syncthreads();
@@ -2505,7 +2648,7 @@ __device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__r
   const int64_t ldq = op.count, ldr = op.bn.n;
   for (int e = tid; e < kk * m; e += kThreads) {
     const int q = e / m, i = e % m;
-    Q[q * ldq + qpos[i]] = Qb[q * m + i];
+    Q[q * ldq + qpos[i]] = Qb[q * mq + i];
   }
   for (int e = tid; e < kk * c; e += kThreads) {
     const int q = e / c, j = e % c;
