@@ -1887,12 +1887,14 @@ __device__ int keep_rank(const double *w, int navail, int n, int ucols, const Ke
 // thread and z_t -= V (T w_t), while the next block's V is staged into the other buffer.
 // Two barriers per four reflectors.
 constexpr int kWY = 4;
-// For up to 64 kept columns: 4 lanes per column (a quad of one wave) each take every 4th
-// row and add their dot products across the quad, one reflector at a time, so no step
-// waits on a workgroup barrier (the quads are independent; the reflectors are read only).
-__device__ void back_transform_quads(const EigWs &E, int k) {
-  const int n = E.n, tid = threadIdx.x, sub = tid & 3, t = tid >> 2;
-  if (t < k) {                               // every lane of the quad takes this branch
+// For up to 64 kept columns: L = 4, 8 or 16 lanes per column (as many as 256 threads give
+// the k columns; an aligned group within one wave) each take every L-th row and add their
+// dot products across the group, one reflector at a time, so no step waits on a workgroup
+// barrier (the groups are independent; the reflectors are read only).
+template <int L>
+__device__ void back_transform_lanes(const EigWs &E, int k) {
+  const int n = E.n, tid = threadIdx.x, sub = tid % L, t = tid / L;
+  if (t < k) {                               // every lane of the group takes this branch
     double *z = E.A + E.isrt[t] * E.pa;
     for (int j = n - 3; j >= 0; --j) {
       const double beta = E.hv[int64_t(n) * n + j];
@@ -1902,25 +1904,30 @@ __device__ void back_transform_quads(const EigWs &E, int k) {
       double *zz = z + j + 1;
       double a0 = 0.0, a1 = 0.0;
       int i = sub;
-      for (; i + 4 < m; i += 8) {
+      for (; i + L < m; i += 2 * L) {
         a0 = fma(v[i], zz[i], a0);
-        a1 = fma(v[i + 4], zz[i + 4], a1);
+        a1 = fma(v[i + L], zz[i + L], a1);
       }
       if (i < m) a0 = fma(v[i], zz[i], a0);
-      const double w = beta * quad_sum(a0 + a1);
+      const double w = beta * lsum(a0 + a1, L);
       int r = sub;                           // loads of 4 rows issued before their stores
-      for (; r + 12 < m; r += 16) {
-        const double v0 = v[r], v1 = v[r + 4], v2 = v[r + 8], v3 = v[r + 12];
-        const double z0 = zz[r], z1 = zz[r + 4], z2 = zz[r + 8], z3 = zz[r + 12];
+      for (; r + 3 * L < m; r += 4 * L) {
+        const double v0 = v[r], v1 = v[r + L], v2 = v[r + 2 * L], v3 = v[r + 3 * L];
+        const double z0 = zz[r], z1 = zz[r + L], z2 = zz[r + 2 * L], z3 = zz[r + 3 * L];
         zz[r] = fma(-w, v0, z0);
-        zz[r + 4] = fma(-w, v1, z1);
-        zz[r + 8] = fma(-w, v2, z2);
-        zz[r + 12] = fma(-w, v3, z3);
+        zz[r + L] = fma(-w, v1, z1);
+        zz[r + 2 * L] = fma(-w, v2, z2);
+        zz[r + 3 * L] = fma(-w, v3, z3);
       }
-      for (; r < m; r += 4) zz[r] = fma(-w, v[r], zz[r]);
+      for (; r < m; r += L) zz[r] = fma(-w, v[r], zz[r]);
     }
   }
   __syncthreads();
+}
+__device__ void back_transform_quads(const EigWs &E, int k) {
+  if (k <= kThreads / 16) back_transform_lanes<16>(E, k);
+  else if (k <= kThreads / 8) back_transform_lanes<8>(E, k);
+  else back_transform_lanes<4>(E, k);
 }
 
 __device__ void back_transform(const EigWs &E, int k) {
