@@ -1386,8 +1386,9 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // Jacobi rotation of the symmetric 4 x 4 a (eigenvectors v) that zeroes a[I][J]: with
 // d = a_JJ - a_II and t = tan of the angle, the smaller root of t^2 + (d / a_IJ) t - 1 = 0,
 // t = sign(d) 2 a_IJ / (|d| + sqrt(d^2 + 4 a_IJ^2)), formed after scaling d and 2 a_IJ by the
-// larger of the two; then a_II -= t a_IJ, a_JJ += t a_IJ. Entries at or below
-// eps (|a_II| + |a_JJ|) / 2 are dropped instead (t = 0).
+// larger of the two (itself first scaled by 2^1000 when below 2^-1000, so that its reciprocal
+// stays finite for subnormal entries); then a_II -= t a_IJ, a_JJ += t a_IJ. Entries at or
+// below eps (|a_II| + |a_JJ|) / 2 are dropped instead (t = 0).
 struct JacRot {
   double t, cs, sn;
   bool rot;
@@ -1398,8 +1399,13 @@ __device__ __forceinline__ JacRot jac4_angle(const double (&a)[4][4]) {
   JacRot R;
   const double aij = a[I][J];
   R.rot = fabs(aij) > 0.5 * kEps * (fabs(a[I][I]) + fabs(a[J][J]));
-  const double d = a[J][J] - a[I][I], g = 2.0 * aij;
-  const double rm = rcp_nr(R.rot ? fmax(fabs(d), fabs(g)) : 1.0);
+  double d = a[J][J] - a[I][I], g = 2.0 * aij, mx = fmax(fabs(d), fabs(g));
+  if (mx < 0x1p-1000) {                                  // exactly rescaled: 1/mx must not overflow
+    d *= 0x1p1000;
+    g *= 0x1p1000;
+    mx *= 0x1p1000;
+  }
+  const double rm = rcp_nr(R.rot ? mx : 1.0);
   const double dn = d * rm, gn = g * rm;
   const double h = fma(dn, dn, gn * gn);                 // in [1, 2]
   const double t = (d >= 0.0 ? gn : -gn) * rcp_nr(fabs(dn) + h * rsq_nr(h));

@@ -104,6 +104,11 @@ def w5_full(T):
     gold = json.load(open(os.path.join(GOLD, "w5_oracle.json")))["rows"]
     nets = inputs.csp_batch(32)
     hs = [T.create_network(n) for n in nets]
+    # plan each formula here (several seconds of host work each, kept on the handle for the
+    # batch) so that the run reports progress while it plans
+    for i, (h, n) in enumerate(zip(hs, nets)):
+        st = T.tn_plan_stats(h, n.slices, 32, 1)
+        print(f"  planned formula {i + 1}/32: {st['ops']} ops", flush=True)
     return gold, nets, hs
 
 
