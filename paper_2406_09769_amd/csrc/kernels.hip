@@ -579,20 +579,42 @@ __device__ bool gemm_op(const Op &op, const double *__restrict__ A, const double
     sc->flops += 2LL * M * N * K;
     if (split) sc->split_flops += 2LL * M * N * K;
   }
-  for (int k = tid; k < K; k += kThreads) {
-    const int ks = box_conv(op.bk_, k);
-    kA[k] = tab[op.ak + ks];
-    kB[k] = tab[op.bk + ks];
-  }
-  for (int m = tid; m < M; m += kThreads) {
-    const int sm = box_conv(op.bm, m);
-    rA[m] = int32_t(map_off(tab, op.am, sm));
-    rC[m] = int32_t(sm * NS);
-  }
-  for (int n = tid; n < N; n += kThreads) {
-    const int sn = box_conv(op.bnb, n);
-    cB[n] = int32_t(map_off(tab, op.bn, sn));
-    cC[n] = sn;
+  if (K <= kThreads && M <= kThreads && N <= kThreads) {
+    // one index of each kind per thread: every table load is issued before the first LDS
+    // store, so the offsets cost one memory round trip
+    int32_t a0 = 0, b0 = 0, h1 = 0, l1 = 0, h2 = 0, l2 = 0, sm = 0, sn = 0;
+    if (tid < K) { const int ks = box_conv(op.bk_, tid); a0 = tab[op.ak + ks]; b0 = tab[op.bk + ks]; }
+    if (tid < M) {
+      sm = box_conv(op.bm, tid);
+      const int32_t h = sm / op.am.lo_n;
+      h1 = tab[op.am.hi + h];
+      l1 = tab[op.am.lo + (sm - h * op.am.lo_n)];
+    }
+    if (tid < N) {
+      sn = box_conv(op.bnb, tid);
+      const int32_t h = sn / op.bn.lo_n;
+      h2 = tab[op.bn.hi + h];
+      l2 = tab[op.bn.lo + (sn - h * op.bn.lo_n)];
+    }
+    if (tid < K) { kA[tid] = a0; kB[tid] = b0; }
+    if (tid < M) { rA[tid] = int32_t(int64_t(h1) + l1); rC[tid] = int32_t(sm * NS); }
+    if (tid < N) { cB[tid] = int32_t(int64_t(h2) + l2); cC[tid] = sn; }
+  } else {
+    for (int k = tid; k < K; k += kThreads) {
+      const int ks = box_conv(op.bk_, k);
+      kA[k] = tab[op.ak + ks];
+      kB[k] = tab[op.bk + ks];
+    }
+    for (int m = tid; m < M; m += kThreads) {
+      const int sm = box_conv(op.bm, m);
+      rA[m] = int32_t(map_off(tab, op.am, sm));
+      rC[m] = int32_t(sm * NS);
+    }
+    for (int n = tid; n < N; n += kThreads) {
+      const int sn = box_conv(op.bnb, n);
+      cB[n] = int32_t(map_off(tab, op.bn, sn));
+      cC[n] = sn;
+    }
   }
   __syncthreads();
   if (split) {
