@@ -1641,7 +1641,8 @@ __device__ void tri_dc(const EigWs &E, const DcBufs &bufs) {
 }
 
 // Tridiagonalise E.A and solve T: by divide and conquer in the buffers dcb when use_dc
-// (order <= kDcMax), else by implicit QL.
+// (order <= kDcMax), else by implicit QL with the Wilkinson shift (the method of the Handbook
+// routine tql2 of Bowdler, Martin, Reinsch and Wilkinson, re-organised for one workgroup).
 __device__ void tri_ql(const EigWs &E, NetScalars *sc, bool timed, bool use_dc = false, DcBufs dcb = DcBufs{}) {
   const int n = E.n, pa = E.pa, tid = threadIdx.x, wave = tid >> 6;
   double *A = E.A, *vv = E.vv, *pp = E.pp, *ww = E.ww, *dd = E.dd, *ee = E.ee, *hv = E.hv;
