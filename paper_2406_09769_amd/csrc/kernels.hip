@@ -2197,7 +2197,19 @@ __device__ void sym_times(const double *A, int pa, const double *V, int n, int p
 // Returns true with U written and the kept rank set; false leaves everything for the
 // exact solve (the reason is counted in sc->rej).
 constexpr double kFroSlack = 1e-13;
-__device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
+// Runtime extents (kept ranks) written by this workgroup are also kept in a small LDS cache:
+// entry (slot & (kDynCache-1)) holds the slot id, then its value, so staging a later op that
+// reads a recent slot needs no memory round trip. dcache may be null (no cache).
+constexpr int kDynCache = 256;
+__device__ __forceinline__ void set_dyn(int32_t *dyn, int32_t *dcache, int32_t slot, int32_t v) {
+  dyn[slot] = v;
+  if (dcache) {
+    dcache[slot & (kDynCache - 1)] = slot;
+    dcache[kDynCache + (slot & (kDynCache - 1))] = v;
+  }
+}
+
+__device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, int32_t *dcache, const KeepParams &kp, NetScalars *sc,
                             double *lds, int n, int ld, int ucols) {
   const int tid = threadIdx.x;
   const bool bonded = op.bm.nd > 0;
@@ -2319,7 +2331,7 @@ __device__ bool eig_learned(const Op &op, double *ws, int32_t *dyn, const KeepPa
       lap(3);
       if (rmax <= kp.residual_tol) {
         if (tid == 0) {
-          dyn[op.out_dyn] = k;
+          set_dyn(dyn, dcache, op.out_dyn, k);
           sc->n_learned += 1;
           sc->max_resid = fmax(sc->max_resid, rmax);
           sc->eig_flops += 9LL * p * p * p + 4LL * n * n * p * (it + 1);
@@ -2366,7 +2378,7 @@ __device__ void harvest_rows(const Op &op, const double *ws, int n, int ld, int 
   __syncthreads();
 }
 
-__device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParams &kp, NetScalars *sc,
+__device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, int32_t *dcache, const KeepParams &kp, NetScalars *sc,
                          double *lds) {
   const int ld = int(op.count);            // static dimension = row stride of L and of U
   const int n = box_eff(op.bm);            // runtime dimension: the valid leading block
@@ -2376,7 +2388,7 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
   // scratch: reflectors first (n^2 + n doubles), then the matrix and Z (n (n + 1))
   const bool big = eig_lds_doubles(n) > kLdsDoubles;
   const bool warm = !(op.flags & F_NO_WARM) && !big;
-  if (kp.model && warm && eig_learned(op, ws, dyn, kp, sc, lds, n, ld, ucols)) return;
+  if (kp.model && warm && eig_learned(op, ws, dyn, dcache, kp, sc, lds, n, ld, ucols)) return;
   // the reflectors stay in LDS when they fit beside the work area (n up to about 90): the
   // reduction's writes and the back-transformation's reads then never wait on memory
   const bool hv_lds = !big && eig_lds_doubles(n) + n * n + n <= kLdsDoubles;
@@ -2415,7 +2427,7 @@ __device__ void eig_keep(const Op &op, double *ws, int32_t *dyn, const KeepParam
       sc->n_fallback += 1;
     }
     E.flag[1] = k;
-    dyn[op.out_dyn] = k;
+    set_dyn(dyn, dcache, op.out_dyn, k);
     sc->eig_flops += 9LL * n * n * n;
   }
   __syncthreads();
@@ -2492,7 +2504,7 @@ static_assert(kQrMaxRows * (kQrMaxCols | 1) + kQrMaxCols * (kQrMaxRows | 1) + 3 
                   (kQrMaxRows + kQrMaxCols) * 3 / 2 + 2 * kQrMaxCols * kQrNb <= kLdsDoubles,
               "the QR of the largest matrix fits LDS");
 static_assert(kQrMaxCols % kQrNb == 0 && (kQrMaxCols / kQrNb) * kQrNb <= kThreads, "one lane per row of every T");
-__device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__restrict__ tab, NetScalars *sc,
+__device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, int32_t *dcache, const int32_t *__restrict__ tab, NetScalars *sc,
                       double *lds) {
   const int m = box_eff(op.bm), c = box_eff(op.bnb), kk = m < c ? m : c;
   const int tid = threadIdx.x, sub = tid & 3, t = tid >> 2;
@@ -2691,7 +2703,7 @@ __device__ void qr_wg(const Op &op, double *ws, int32_t *dyn, const int32_t *__r
     R[q * ldr + rpos[j]] = j > q ? X[q * pitch + j] : (j == q ? rdiag[q] : 0.0);
   }
   if (tid == 0) {
-    dyn[op.out_dyn] = kk;
+    set_dyn(dyn, dcache, op.out_dyn, kk);
     sc->eig_flops += 4LL * m * c * kk;
   }
   __syncthreads();
@@ -2711,14 +2723,17 @@ __device__ __forceinline__ int32_t op_word(const NetDev &nd, int64_t i) {
 
 // Stage an op from its words (one per thread) into LDS, then replace its Box slot ids
 // by the runtime extents those slots hold.
-__device__ void stage_op_words(const NetDev &nd, int32_t w, Op &s_op) {
+__device__ void stage_op_words(const NetDev &nd, int32_t w, Op &s_op, const int32_t *dcache = nullptr) {
   const int tid = threadIdx.x;
   if (tid < kOpWords) reinterpret_cast<int32_t *>(&s_op)[tid] = w;
   __syncthreads();
   if (tid < 3 * kMaxDyn) {
     Box *bx = tid < kMaxDyn ? &s_op.bm : (tid < 2 * kMaxDyn ? &s_op.bnb : &s_op.bk_);
     const int d = tid % kMaxDyn;
-    if (d < bx->nd) bx->id[d] = nd.dyn[bx->id[d]];
+    if (d < bx->nd) {
+      const int32_t id = bx->id[d], e = id & (kDynCache - 1);
+      bx->id[d] = dcache && dcache[e] == id ? dcache[kDynCache + e] : nd.dyn[id];
+    }
   }
   __syncthreads();
 }
@@ -2731,6 +2746,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
   __shared__ double lds[kLdsDoubles];
   __shared__ Op s_op;                 // the current op, Box slot ids replaced by extents
   __shared__ NetScalars s_sc;         // the network's scalars while the workgroup runs
+  __shared__ int32_t s_dyc[2 * kDynCache];   // recent kept ranks: slot ids, then values
   constexpr int kScWords = int(sizeof(NetScalars) / 8);
   static_assert(kScWords <= kThreads, "NetScalars is copied by one pass of the workgroup");
   NetDev nd = nets[blockIdx.x];
@@ -2739,6 +2755,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
   // counters and sums are updated by one thread after most ops; kept in LDS, no update
   // waits on a memory round trip before the next barrier
   if (tid < kScWords) reinterpret_cast<long long *>(&s_sc)[tid] = reinterpret_cast<const long long *>(g_sc)[tid];
+  for (int e = tid; e < kDynCache; e += kThreads) s_dyc[e] = -1;   // no slot cached yet
   __syncthreads();
   nd.sc = &s_sc;
   if (first < 0) {                    // a part of a chunked batch: the descriptor's range
@@ -2750,7 +2767,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
   // per launch, so each descriptor would otherwise cost a full memory round trip
   int32_t w = first < end ? op_word(nd, first) : 0;
   for (int64_t i = first; i < end; ++i) {
-    stage_op_words(nd, w, s_op);
+    stage_op_words(nd, w, s_op, s_dyc);
     if (i + 1 < end) w = op_word(nd, i + 1);
     const Op &op = s_op;
     const int kind = op.kind;
@@ -2764,7 +2781,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
         break;
       }
       case OP_EIG:
-        eig_keep(op, nd.ws, nd.dyn, kp, nd.sc, lds);
+        eig_keep(op, nd.ws, nd.dyn, s_dyc, kp, nd.sc, lds);
         break;
       case OP_RESCALE:
         rescale_wg(op, nd.ws + op.c, nd.sc, lds);
@@ -2776,7 +2793,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(const NetDev *__restri
         ident_wg(nd.ws + op.c, op.count);
         break;
       case OP_QR:
-        qr_wg(op, nd.ws, nd.dyn, nd.tab, nd.sc, lds);
+        qr_wg(op, nd.ws, nd.dyn, s_dyc, nd.tab, nd.sc, lds);
         break;
       default:
         break;
