@@ -39,7 +39,7 @@ PEAK_16BIT_TFLOPS = 2500.0      # MI355X dense BF16 / FP16 matrix cores
 # HBM bytes per launch of interp_kernel on this workload: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (factors from a 256 MiB copy), from profiles/interp_kernel_w2_64x64_fp64_hbm.txt. None
 # whenever the kernel has changed since the counters were taken.
-TRAFFIC_BYTES = 3.692e9
+TRAFFIC_BYTES = 3.687e9
 SPLIT_TAU_REL = 1e-10   # keep cutoff of the split-precision forms (relative to the largest eigenvalue)
 BOUND = 1e-8            # accuracy the forms are counted at (per site, against the oracle)
 
