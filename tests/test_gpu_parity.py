@@ -142,13 +142,13 @@ def test_repeat_calls_are_deterministic(T):
 
 
 def test_w2_full_size_against_golden(T):
-    """64x64 lattices at the 8 betas, chi 32, env 1 and 2, one launch per (chi, env);
+    """64x64 lattices at the 8 betas, chi 32 and 64, env 1 and 2, one launch per (chi, env);
     expected values written by tests/golden/make_golden.py from the oracle."""
     path = os.path.join(HERE, "golden", "w2_oracle.json")
     gold = json.load(open(path))["rows"]
     nets = [inputs.ising_2d(64, 64, b) for b in inputs.w2_betas()]
     hs = [T.create_network(n) for n in nets]
-    for chi, env in ((32, 1), (32, 2)):
+    for chi, env in ((32, 1), (32, 2), (64, 1), (64, 2)):
         rs = T.tn_contract_approx_batch(hs, [n.slices for n in nets], chi, env)
         for net, b, r in zip(nets, inputs.w2_betas(), rs):
             g = next(x for x in gold if x["chi"] == chi and x["env"] == env and abs(x["beta"] - b) < 1e-12)
