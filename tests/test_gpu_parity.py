@@ -195,7 +195,7 @@ def test_w3_chi32_against_golden(T):
     bit-identical to keeping them all). Same 1e-10 bound as at chi 16."""
     path = os.path.join(HERE, "golden", "w3_chi32_oracle.json")
     if not os.path.exists(path):
-        pytest.skip("no stored chi 32 oracle value (make_golden.py w3chi32 writes it in about 3 hours)")
+        pytest.skip("no stored chi 32 oracle value (make_golden.py w3chi32 writes it in about 6.5 hours)")
     for g in json.load(open(path))["rows"]:
         net = inputs.ising_3d(8, 8, 8, g["beta"])
         h = T.create_network(net)
